@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/bench and by the oracle.
+
+This module holds geometry and random numbers only: density profiles are built
+from coexistence densities and widths that the caller passes in, so none of the
+two-phase method's arithmetic (equation of state, Maxwell construction, forcing,
+collision) lives here.
+
+Layout convention for every field: node index n = x + nx*(y + ny*z), float64;
+velocity fields are structure-of-arrays, shape (D, N).
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used as a counter-based generator:
+draw n of stream `seed` is mix(seed + (n + 1) * gamma), gamma = 0x9E3779B97F4A7C15.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Draws start..start+count-1 of the SplitMix64 stream `seed` (uint64)."""
+    with np.errstate(over="ignore"):
+        n = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + n * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm(seed: int, count: int, amplitude: float) -> np.ndarray:
+    """Uniform numbers in [-amplitude, amplitude) from 53-bit SplitMix64 mantissas."""
+    u = (splitmix64(seed, count) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return amplitude * (2.0 * u - 1.0)
+
+
+def _grid(nx: int, ny: int, nz: int):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x.ravel().astype(np.float64), y.ravel().astype(np.float64), z.ravel().astype(np.float64)
+
+
+def tanh_profile(d: np.ndarray, rho_liquid: float, rho_vapour: float, width: float) -> np.ndarray:
+    """rho = mean + half-jump * tanh(2 d / width); d > 0 inside the liquid.
+
+    With this form the maximum slope is (rho_l - rho_v)/width, so `width` equals
+    the interface width (rho_l - rho_v)/max|grad rho|.
+    """
+    mean = 0.5 * (rho_liquid + rho_vapour)
+    half = 0.5 * (rho_liquid - rho_vapour)
+    return mean + half * np.tanh(2.0 * d / width)
+
+
+def add_noise(rho: np.ndarray, seed: int, amplitude: float) -> np.ndarray:
+    """Multiplicative noise rho * (1 + eta), eta ~ U(-amplitude, amplitude) per node."""
+    if amplitude == 0.0:
+        return rho.copy()
+    return rho * (1.0 + uniform_pm(seed, rho.size, amplitude))
+
+
+def flat_slab(nx: int, ny: int, nz: int, rho_liquid: float, rho_vapour: float, width: float,
+              lo: float | None = None, hi: float | None = None, axis: int = 0,
+              noise: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Liquid slab occupying [lo, hi) along `axis` (default: the middle half), tanh walls."""
+    n_axis = (nx, ny, nz)[axis]
+    lo = n_axis / 4.0 if lo is None else lo
+    hi = 3.0 * n_axis / 4.0 if hi is None else hi
+    coords = _grid(nx, ny, nz)[axis]
+    # interfaces sit half-way between nodes lo-1 | lo and hi-1 | hi
+    d = np.minimum(coords - (lo - 0.5), (hi - 0.5) - coords)
+    rho = tanh_profile(d, rho_liquid, rho_vapour, width)
+    return add_noise(rho, seed, noise)
+
+
+def drop(nx: int, ny: int, nz: int, radius: float, rho_liquid: float, rho_vapour: float,
+         width: float, centre=None, noise: float = 0.0, seed: int = 0, bubble: bool = False) -> np.ndarray:
+    """Circular (nz == 1) or spherical drop of the liquid in vapour (or a bubble if `bubble`)."""
+    x, y, z = _grid(nx, ny, nz)
+    if centre is None:
+        centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
+    cx, cy, cz = centre
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + ((z - cz) ** 2 if nz > 1 else 0.0))
+    d = radius - r
+    if bubble:
+        d = -d
+    rho = tanh_profile(d, rho_liquid, rho_vapour, width)
+    return add_noise(rho, seed, noise)
+
+
+def zero_velocity(D: int, N: int) -> np.ndarray:
+    return np.zeros((D, N), dtype=np.float64)
+
+
+def liquid_fraction(rho: np.ndarray, rho_liquid: float, rho_vapour: float) -> np.ndarray:
+    return np.clip((rho - rho_vapour) / (rho_liquid - rho_vapour), 0.0, 1.0)
+
+
+def pillar_mask(nx: int, ny: int, nz: int, pillar: int = 8, gap: int = 8, height: int = 16) -> np.ndarray:
+    """Solid floor at z = 0 plus square pillars (x mod p < w, y mod p < w, 1 <= z <= height).
+
+    Returns uint8, 1 = solid. Periodic wrap in z makes the floor a ceiling as well.
+    """
+    x, y, z = _grid(nx, ny, nz)
+    x = x.astype(np.int64); y = y.astype(np.int64); z = z.astype(np.int64)
+    period = pillar + gap
+    solid = (z == 0) | (((x % period) < pillar) & ((y % period) < pillar) & (z >= 1) & (z <= height))
+    return solid.astype(np.uint8)
+
+
+def random_mask(nx: int, ny: int, nz: int, fraction: float, seed: int) -> np.ndarray:
+    """Sparse random solid nodes (for bounce-back parity on tiny grids)."""
+    u = (splitmix64(seed, nx * ny * nz) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (u < fraction).astype(np.uint8)
+
+
+def random_state(N: int, D: int, rho_lo: float, rho_hi: float, umax: float, seed: int):
+    """Random density in [rho_lo, rho_hi) and velocity components in [-umax, umax)."""
+    u01 = (splitmix64(seed, N) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    rho = rho_lo + (rho_hi - rho_lo) * u01
+    u = np.stack([uniform_pm(seed + 7919 * (a + 1), N, umax) for a in range(D)])
+    return rho, u
+
+
+@dataclass(frozen=True)
+class SweepCase:
+    """One flat-interface case of the batched temperature sweep (D2Q9, ny x L periodic)."""
+    index: int
+    T_reduced: float
+    nx: int          # length across the interface (x)
+    ny: int          # width (y)
+    fp64: bool
+
+
+def temperature_sweep(ncases: int = 64, t_lo: float = 0.55, t_hi: float = 0.99,
+                      l_lo: int = 128, l_hi: int = 2048, width: int = 4,
+                      fp64_from: float = 0.95) -> list[SweepCase]:
+    """Uniformly spaced reduced temperatures; lengths log-spaced and increasing with T."""
+    cases = []
+    for k in range(ncases):
+        s = k / (ncases - 1) if ncases > 1 else 0.0
+        tr = t_lo + (t_hi - t_lo) * s
+        length = int(round(l_lo * (l_hi / l_lo) ** s))
+        cases.append(SweepCase(k, tr, length, width, tr >= fp64_from))
+    return cases
+
+
+def impact_drop_velocity(rho: np.ndarray, rho_liquid: float, rho_vapour: float, D: int,
+                         speed: float, axis: int) -> np.ndarray:
+    """Velocity `speed` along `axis` weighted by the liquid fraction (drop-impact start)."""
+    u = np.zeros((D, rho.size))
+    u[axis] = speed * liquid_fraction(rho, rho_liquid, rho_vapour)
+    return u
+
+
+def log_spaced_int(lo: int, hi: int, count: int) -> list[int]:
+    return [int(round(lo * (hi / lo) ** (k / (count - 1)))) for k in range(count)]
+
+
+__all__ = [
+    "splitmix64", "uniform_pm", "tanh_profile", "add_noise", "flat_slab", "drop", "zero_velocity",
+    "liquid_fraction", "pillar_mask", "random_mask", "random_state", "SweepCase", "temperature_sweep",
+    "impact_drop_velocity", "log_spaced_int",
+]

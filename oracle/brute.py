@@ -1,0 +1,136 @@
+"""Independent vectorised NumPy step for tiny grids (pins lbm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY. Written separately from lbm_oracle.c in a different
+style: populations live in a velocity cube indexed by (c_x+1, c_y+1[, c_z+1]),
+shifts are np.roll over whole fields, streaming is written in pull form and the
+product form (Sec. 2.3.2, eq prod) is an outer product of per-axis Psi triplets.
+The equation of state comes from thermo.Fluid.
+
+Step, with the readings used throughout the oracle: S = -F for the discrete
+Korteweg force of eq Kforce_final, xi* = u + S/rho, zeta* = 1/3 + xi*^2 + Phi/rho,
+Phi = (1 - omega/2) d_a(rho u_a^3) by central differences, halfway bounce-back.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from .thermo import Fluid
+
+AXIS_W = np.array([1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0])   # Psi_{-1,0,+1}(0, 1/3)
+
+
+def _velocities(D):
+    return list(itertools.product((-1, 0, 1), repeat=D))   # tuples (cx, cy[, cz])
+
+
+def _psi_triplet(xi, zeta):
+    """Stack [Psi_-1, Psi_0, Psi_+1](xi, zeta) along a new leading axis."""
+    return np.stack([0.5 * (zeta - xi), 1.0 - zeta, 0.5 * (zeta + xi)])
+
+
+def _cube(rho, xis, zetas):
+    """rho * prod_a Psi_{c_a}(xi_a, zeta_a) as a (3,)*D + grid array."""
+    trip = [_psi_triplet(x, z) for x, z in zip(xis, zetas)]
+    if len(trip) == 2:
+        return rho[None, None] * trip[0][:, None] * trip[1][None, :]
+    return rho[None, None, None] * trip[0][:, None, None] * trip[1][None, :, None] * trip[2][None, None, :]
+
+
+def _roll(field, c, k=1):
+    """field(r + k c) for every r (periodic); grid axes are ordered (z, y, x) or (y, x)."""
+    D = len(c)
+    shifts = tuple(-k * c[a] for a in reversed(range(D)))
+    return np.roll(field, shifts, axis=tuple(range(field.ndim - D, field.ndim)))
+
+
+class BruteForce:
+    """Tiny-grid FP64 reference: state f[(c)] on a grid of shape (ny, nx) or (nz, ny, nx)."""
+
+    def __init__(self, D, shape, fluid: Fluid, kappa, tau, rho_wall=0.0, mask=None,
+                 tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0):
+        self.D, self.shape = D, tuple(shape)
+        self.fluid, self.kappa = fluid, kappa
+        self.tau, self.tau_v, self.rl, self.rv = tau, tau_vapour, rho_liquid, rho_vapour
+        self.rho_wall = rho_wall
+        self.solid = np.zeros(self.shape, bool) if mask is None else mask.reshape(self.shape).astype(bool)
+        self.vel = _velocities(D)
+        self.wcube = AXIS_W
+        for _ in range(D - 1):
+            self.wcube = np.multiply.outer(self.wcube, AXIS_W)
+
+    def _idx(self, c):
+        return tuple(ci + 1 for ci in c)
+
+    def init(self, rho, u=None):
+        rho = rho.reshape(self.shape)
+        u = np.zeros((self.D,) + self.shape) if u is None else u.reshape((self.D,) + self.shape)
+        self.f = _cube(rho, list(u), [1.0 / 3.0 + ua * ua for ua in u])
+        self.f[(slice(None),) * self.D + (self.solid,)] = 0.0
+        return self
+
+    def _omega(self, rho):
+        if self.tau_v <= 0.0:
+            return np.full_like(rho, 1.0 / self.tau)
+        nl, nv = (self.tau - 0.5) / 3.0, (self.tau_v - 0.5) / 3.0
+        s = np.clip((rho - self.rv) / (self.rl - self.rv), 0.0, 1.0)
+        return 1.0 / (3.0 * (nv + (nl - nv) * s) + 0.5)
+
+    def fields(self):
+        D = self.D
+        vaxes = tuple(range(D))
+        rho = self.f.sum(axis=vaxes)
+        j = []
+        for a in range(D):
+            ca = np.array([-1.0, 0.0, 1.0]).reshape([3 if b == a else 1 for b in range(D)] + [1] * D)
+            j.append((ca * self.f).sum(axis=vaxes))
+        rho = np.where(self.solid, self.rho_wall, rho)
+        u = np.stack([np.where(self.solid, 0.0, ja / rho) for ja in j])
+        P = self.fluid.pressure(rho)
+        P0 = rho / 3.0
+        psi = np.sqrt(np.abs(P - P0))
+        sgn = np.where(P > P0, 1.0, -1.0)
+        Fpsi = np.zeros((D,) + self.shape)
+        Fcap = np.zeros((D,) + self.shape)
+        for c in self.vel:
+            w3 = 3.0 * self.wcube[self._idx(c)]
+            tp = w3 * ((4.0 / 3.0) * _roll(psi, c, 1) - (1.0 / 6.0) * _roll(psi, c, 2))
+            tc = w3 * (2.0 * _roll(rho, c, 1) - _roll(rho, c, 2))
+            for a in range(D):
+                if c[a]:
+                    Fpsi[a] += c[a] * tp
+                    Fcap[a] += c[a] * tc
+        F = 2.0 * sgn * psi * Fpsi + self.kappa * rho * Fcap
+        S = np.where(self.solid, 0.0, -F)
+        return rho, u, S
+
+    def step(self, n=1):
+        D = self.D
+        for _ in range(n):
+            rho, u, S = self.fields()
+            om = self._omega(rho)
+            g = rho * u ** 3
+            Phi = []
+            for a in range(D):
+                e = tuple(1 if b == a else 0 for b in range(D))
+                Phi.append((1.0 - 0.5 * om) * 0.5 * (_roll(g[a], e, 1) - _roll(g[a], e, -1)))
+            xs = [u[a] + S[a] / rho for a in range(D)]
+            feq = _cube(rho, list(u), [1.0 / 3.0 + u[a] ** 2 for a in range(D)])
+            fst = _cube(rho, xs, [1.0 / 3.0 + xs[a] ** 2 + Phi[a] / rho for a in range(D)])
+            fpost = self.f + om * (feq - self.f) + (fst - feq)
+            fnew = np.zeros_like(self.f)
+            for c in self.vel:
+                i = self._idx(c)
+                ib = self._idx(tuple(-ci for ci in c))
+                arrived = _roll(fpost[i], c, -1)            # value from r - c
+                src_solid = _roll(self.solid, c, -1)
+                fnew[i] = np.where(src_solid, fpost[ib], arrived)
+            fnew[(slice(None),) * D + (self.solid,)] = 0.0
+            self.f = fnew
+        return self
+
+    def moments(self):
+        rho, u, S = self.fields()
+        U = np.where(self.solid[None], 0.0, u + S / (2.0 * rho))
+        return rho.ravel(), U.reshape(self.D, -1)

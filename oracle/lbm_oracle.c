@@ -1,0 +1,417 @@
+/*
+ * lbm_oracle.c -- plain, slow FP64 reference of the two-phase lattice BGK step of
+ * Hosseini, Dorschner & Karlin, "Towards a consistent lattice Boltzmann model for
+ * two-phase fluid" (Sec. 2.3).
+ *
+ * TEST INFRASTRUCTURE ONLY. The only callers are tests/, __graft_entry__.smoke()
+ * and bench.py's CPU-baseline leg. It shares no code, header or table with the HIP
+ * library; its lattice tables are generated here from the product form.
+ *
+ * One step t -> t+1 reads every neighbour at time t (a Jacobi update) and follows
+ * the paper's construction in order:
+ *   1. moments rho = sum_i f_i, rho u = sum_i c_i f_i (Sec. 2.3.3); a solid node
+ *      carries the virtual wall density rho_w and u = 0 (Sec. 4.5);
+ *   2. equation of state P(rho) (Sec. 3.1), reference pressure P0 = rho/3 (end of
+ *      Sec. 2.3), pseudo-potential psi = sqrt|P - P0| and its sign (eq force_form);
+ *   3. discrete Korteweg force (eq Kforce_final): pseudo-potential pair
+ *      G1 = 4/3, G2 = -1/6 (eqs PPcond1, PPcond2) and capillary pair (2, -1) kappa;
+ *   4. momentum source S = -F (reading: the kinetic model eq gen_kinetic_model_ext
+ *      enters the force with a minus sign; the literal sign is kept as a test-only
+ *      variant);
+ *   5. diagonal correction Phi_aa = (1 - omega/2) d_a(rho u_a^3) (eq correction with
+ *      P0 = rho/3), d_a by the central difference of the two axis neighbours;
+ *   6. equilibrium f_eq = rho prod Psi(u_a, 1/3 + u_a^2) (eq LBMeq) and extended
+ *      equilibrium f* = rho prod Psi(xi*_a, zeta*_a) (eq LBMstar) with
+ *      xi* = u + S/rho and zeta* = 1/3 + xi*^2 + Phi/rho (reading of eq zetastar
+ *      that makes f* the equilibrium at the incremented velocity when Phi = 0);
+ *   7. LBGK update f + omega (f_eq - f) + (f* - f_eq) (eq LBGK) and streaming to
+ *      r + c_i; a link whose target is solid is reflected back into the opposite
+ *      population of its own node (halfway bounce-back).
+ * Output velocity U = u + S/(2 rho) (Sec. 2.3.5, Appendix D).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int lattice;            /* 2 = D2Q9, 3 = D3Q27 */
+    int nx, ny, nz;
+    int eos;                /* 0 vdW, 1 PR, 2 RKS, 3 CS, 4 ideal (P = rho/3) */
+    double a, b, R, acentric, T_reduced;
+    double kappa;
+    double tau_liquid, tau_vapour, rho_liquid, rho_vapour;
+    double rho_wall;
+    int variant;            /* test-only switches: 1 literal zeta*, 2 literal force sign, 4 no Phi */
+} orc_params;
+
+typedef struct {
+    orc_params p;
+    int D, Q;
+    long N;
+    int c[27][3];
+    double w[27];
+    int opp[27];
+    double T, aalpha;
+    unsigned char *mask;    /* NULL = fully periodic */
+    double *f, *fn;         /* [Q][N], pre-collision populations at time t */
+    double *rho, *u, *psi, *sgn, *g, *S; /* u, g, S: [3][N] */
+} orc_ctx;
+
+/* ---- lattice from the product form (eqs d3q27vel, prod, wi) ---- */
+static double psi_c(int c, double xi, double zeta)
+{
+    if (c == 0) return 1.0 - zeta;
+    if (c == 1) return 0.5 * (xi + zeta);
+    return 0.5 * (-xi + zeta);
+}
+
+int orc_lattice(int D, int *c, double *w, int *opp)
+{
+    int Q = (D == 3) ? 27 : 9;
+    int i = 0;
+    for (int cz = (D == 3 ? -1 : 0); cz <= (D == 3 ? 1 : 0); ++cz)
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) {
+                int v[3] = {cx, cy, cz};
+                double wi = 1.0;
+                for (int a = 0; a < D; ++a) wi *= psi_c(v[a], 0.0, 1.0 / 3.0);
+                if (c) { c[3 * i] = cx; c[3 * i + 1] = cy; c[3 * i + 2] = cz; }
+                if (w) w[i] = wi;
+                ++i;
+            }
+    if (opp)
+        for (int k = 0; k < Q; ++k) opp[k] = Q - 1 - k;  /* enumeration is point-symmetric */
+    return Q;
+}
+
+/* rho * prod_a Psi_{c_ia}(xi_a, zeta_a) for every i (eq prod) */
+void orc_product_form(int D, double rho, const double *xi, const double *zeta, double *out)
+{
+    int c[27 * 3];
+    int Q = orc_lattice(D, c, NULL, NULL);
+    for (int i = 0; i < Q; ++i) {
+        double v = rho;
+        for (int a = 0; a < D; ++a) v *= psi_c(c[3 * i + a], xi[a], zeta[a]);
+        out[i] = v;
+    }
+}
+
+/* ---- equation of state (Sec. 3.1) ---- */
+static double crit_temperature(const orc_params *p)
+{
+    switch (p->eos) {
+    case 0: return 8.0 * p->a / (27.0 * p->b * p->R);
+    case 1: return 0.0778 * p->a / (0.45724 * p->b * p->R);
+    case 2: return 0.08664 * p->a / (0.42748 * p->b * p->R);
+    case 3: return 0.18727 * p->a / (0.4963 * p->b * p->R);
+    default: return 1.0 / 3.0;
+    }
+}
+
+static double alpha_T(const orc_params *p)
+{
+    double w = p->acentric, m;
+    if (p->eos == 1) m = 0.37464 + 1.54226 * w - 0.26992 * w * w;
+    else if (p->eos == 2) m = 0.480 + 1.574 * w - 0.176 * w * w;
+    else return 1.0;
+    double s = 1.0 + m * (1.0 - sqrt(p->T_reduced));
+    return s * s;
+}
+
+static double eos_pressure(const orc_ctx *x, double rho)
+{
+    const orc_params *p = &x->p;
+    double RT = p->R * x->T, b = p->b;
+    switch (p->eos) {
+    case 0: return rho * RT / (1.0 - b * rho) - p->a * rho * rho;
+    case 1: return rho * RT / (1.0 - b * rho) - x->aalpha * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+    case 2: return rho * RT / (1.0 - b * rho) - x->aalpha * rho * rho / (1.0 + b * rho);
+    case 3: {
+        double e = 0.25 * b * rho;
+        return rho * RT * (1.0 + e + e * e - e * e * e) / ((1.0 - e) * (1.0 - e) * (1.0 - e)) - p->a * rho * rho;
+    }
+    default: return rho / 3.0;
+    }
+}
+
+double orc_pressure(const void *h, double rho) { return eos_pressure((const orc_ctx *)h, rho); }
+double orc_temperature(const void *h) { return ((const orc_ctx *)h)->T; }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---- grid helpers ---- */
+static long wrap(long v, long n) { long r = v % n; return r < 0 ? r + n : r; }
+
+static long nbr(const orc_ctx *x, long n, int k, const int *c)
+{
+    long nx = x->p.nx, ny = x->p.ny, nz = x->p.nz;
+    long ix = n % nx, iy = (n / nx) % ny, iz = n / (nx * ny);
+    ix = wrap(ix + k * c[0], nx);
+    iy = wrap(iy + k * c[1], ny);
+    iz = wrap(iz + k * c[2], nz);
+    return ix + nx * (iy + ny * iz);
+}
+
+static int solid(const orc_ctx *x, long n) { return x->mask && x->mask[n]; }
+
+/* relaxation parameter: constant 1/tau, or nu linear in rho between the bulk phases */
+static double omega_at(const orc_ctx *x, double rho)
+{
+    const orc_params *p = &x->p;
+    if (p->tau_vapour <= 0.0) return 1.0 / p->tau_liquid;
+    double nl = (p->tau_liquid - 0.5) / 3.0, nv = (p->tau_vapour - 0.5) / 3.0;
+    double s = (rho - p->rho_vapour) / (p->rho_liquid - p->rho_vapour);
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    double nu = nv + (nl - nv) * s;
+    return 1.0 / (3.0 * nu + 0.5);
+}
+
+/* ---- lifecycle ---- */
+void orc_destroy(void *h)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    if (!x) return;
+    free(x->mask); free(x->f); free(x->fn); free(x->rho); free(x->u);
+    free(x->psi); free(x->sgn); free(x->g); free(x->S);
+    free(x);
+}
+
+void *orc_create(const orc_params *p, const unsigned char *mask)
+{
+    if (!p || (p->lattice != 2 && p->lattice != 3) || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
+    if (p->lattice == 2 && p->nz != 1) return NULL;
+    orc_ctx *x = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    if (!x) return NULL;
+    x->p = *p;
+    x->D = p->lattice;
+    int cf[27 * 3];
+    x->Q = orc_lattice(x->D, cf, x->w, x->opp);
+    for (int i = 0; i < x->Q; ++i)
+        for (int a = 0; a < 3; ++a) x->c[i][a] = cf[3 * i + a];
+    x->N = (long)p->nx * p->ny * p->nz;
+    x->T = p->T_reduced * crit_temperature(p);
+    x->aalpha = p->a * alpha_T(p);
+    long N = x->N;
+    x->f = (double *)calloc((size_t)x->Q * N, sizeof(double));
+    x->fn = (double *)calloc((size_t)x->Q * N, sizeof(double));
+    x->rho = (double *)calloc(N, sizeof(double));
+    x->u = (double *)calloc(3 * N, sizeof(double));
+    x->psi = (double *)calloc(N, sizeof(double));
+    x->sgn = (double *)calloc(N, sizeof(double));
+    x->g = (double *)calloc(3 * N, sizeof(double));
+    x->S = (double *)calloc(3 * N, sizeof(double));
+    if (!x->f || !x->fn || !x->rho || !x->u || !x->psi || !x->sgn || !x->g || !x->S) { orc_destroy(x); return NULL; }
+    if (mask) {
+        x->mask = (unsigned char *)malloc(N);
+        if (!x->mask) { orc_destroy(x); return NULL; }
+        memcpy(x->mask, mask, N);
+    }
+    return x;
+}
+
+/* f = f_eq(rho0, u0) at fluid nodes (u0 may be NULL = at rest) */
+int orc_init(void *h, const double *rho0, const double *u0)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    long N = x->N;
+    int D = x->D, Q = x->Q;
+    for (long n = 0; n < N; ++n) {
+        double feq[27], xi[3] = {0, 0, 0}, zeta[3];
+        if (solid(x, n)) { for (int i = 0; i < Q; ++i) x->f[i * N + n] = 0.0; continue; }
+        for (int a = 0; a < D; ++a) {
+            xi[a] = u0 ? u0[a * N + n] : 0.0;
+            zeta[a] = 1.0 / 3.0 + xi[a] * xi[a];
+        }
+        orc_product_form(D, rho0[n], xi, zeta, feq);
+        for (int i = 0; i < Q; ++i) x->f[i * N + n] = feq[i];
+    }
+    return 0;
+}
+
+/* steps 1-4: moments, EOS, pseudo-potential, g = rho u^3, source S = -F_K */
+static void fields(orc_ctx *x)
+{
+    long N = x->N;
+    int D = x->D, Q = x->Q;
+    const orc_params *p = &x->p;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double r, j[3] = {0, 0, 0};
+        if (solid(x, n)) {
+            r = p->rho_wall;
+        } else {
+            r = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                double fi = x->f[i * N + n];
+                r += fi;
+                for (int a = 0; a < 3; ++a) j[a] += x->c[i][a] * fi;
+            }
+        }
+        x->rho[n] = r;
+        for (int a = 0; a < 3; ++a) {
+            double ua = solid(x, n) ? 0.0 : j[a] / r;
+            x->u[a * N + n] = (a < D) ? ua : 0.0;
+            x->g[a * N + n] = (a < D) ? r * ua * ua * ua : 0.0;
+        }
+        double P = eos_pressure(x, r), P0 = r / 3.0;
+        x->psi[n] = sqrt(fabs(P - P0));
+        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
+    }
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
+            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
+            double wc = 3.0 * x->w[i] * (2.0 * x->rho[n1] - x->rho[n2]);
+            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
+        }
+        for (int a = 0; a < 3; ++a) {
+            double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + p->kappa * x->rho[n] * Fc[a];
+            double s = (p->variant & 2) ? F : -F;
+            x->S[a * N + n] = (solid(x, n) || a >= D) ? 0.0 : s;
+        }
+    }
+}
+
+/* steps 5-7 at one node: f -> f_post; S and Phi given; returns rho via *rho_out */
+static void collide_node(const orc_ctx *x, const double *f, const double *S, const double *Phi,
+                         double omega, double *out)
+{
+    int D = x->D, Q = x->Q;
+    double r = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        r += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += x->c[i][a] * f[i];
+    }
+    double u[3], xi[3], zeq[3], zst[3], feq[27], fst[27];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = j[a] / r;
+        xi[a] = u[a] + S[a] / r;
+        zeq[a] = 1.0 / 3.0 + u[a] * u[a];
+        if (x->p.variant & 1)
+            zst[a] = 1.0 / 3.0 + u[a] * u[a] + Phi[a] / r;
+        else
+            zst[a] = 1.0 / 3.0 + xi[a] * xi[a] + Phi[a] / r;
+    }
+    orc_product_form(D, r, u, zeq, feq);
+    orc_product_form(D, r, xi, zst, fst);
+    for (int i = 0; i < Q; ++i) out[i] = f[i] + omega * (feq[i] - f[i]) + (fst[i] - feq[i]);
+}
+
+void orc_collide(const void *h, const double *f, const double *S, const double *Phi, double omega, double *out)
+{
+    collide_node((const orc_ctx *)h, f, S, Phi, omega, out);
+}
+
+void orc_step(void *h, long steps)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    long N = x->N;
+    int D = x->D, Q = x->Q;
+    for (long t = 0; t < steps; ++t) {
+        fields(x);
+        memset(x->fn, 0, sizeof(double) * (size_t)Q * N);
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < N; ++n) {
+            if (solid(x, n)) continue;
+            double f[27], fp[27], S[3], Phi[3] = {0, 0, 0};
+            for (int i = 0; i < Q; ++i) f[i] = x->f[i * N + n];
+            double omega = omega_at(x, x->rho[n]);
+            for (int a = 0; a < 3; ++a) S[a] = x->S[a * N + n];
+            if (!(x->p.variant & 4))
+                for (int a = 0; a < D; ++a) {
+                    int e[3] = {0, 0, 0};
+                    e[a] = 1;
+                    long np = nbr(x, n, 1, e), nm = nbr(x, n, -1, e);
+                    Phi[a] = (1.0 - 0.5 * omega) * 0.5 * (x->g[a * N + np] - x->g[a * N + nm]);
+                }
+            collide_node(x, f, S, Phi, omega, fp);
+            for (int i = 0; i < Q; ++i) {
+                long d = nbr(x, n, 1, x->c[i]);
+                if (solid(x, d))
+                    x->fn[x->opp[i] * N + n] = fp[i];
+                else
+                    x->fn[i * N + d] = fp[i];
+            }
+        }
+        double *tmp = x->f; x->f = x->fn; x->fn = tmp;
+    }
+}
+
+/* rho (N), U = u + S/(2 rho) ([D][N]), totals = {sum rho, sum rho u_x, _y, _z} over fluid nodes */
+void orc_moments(void *h, double *rho, double *U, double *totals)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    long N = x->N;
+    int D = x->D;
+    fields(x);
+    double M = 0.0, J[3] = {0, 0, 0};
+    for (long n = 0; n < N; ++n) {
+        double r = x->rho[n];
+        if (rho) rho[n] = r;
+        for (int a = 0; a < D; ++a)
+            if (U) U[a * N + n] = solid(x, n) ? 0.0 : x->u[a * N + n] + x->S[a * N + n] / (2.0 * r);
+        if (!solid(x, n)) {
+            M += r;
+            for (int a = 0; a < D; ++a) J[a] += r * x->u[a * N + n];
+        }
+    }
+    if (totals) { totals[0] = M; totals[1] = J[0]; totals[2] = J[1]; totals[3] = J[2]; }
+}
+
+/* momentum source S = -F_K of the current state, [3][N] */
+void orc_source(void *h, double *S)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    fields(x);
+    memcpy(S, x->S, sizeof(double) * 3 * (size_t)x->N);
+}
+
+/* F_K of eq Kforce_final for a given density field (all nodes read as given) */
+void orc_korteweg_force(void *h, const double *rho, double *F)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    long N = x->N;
+    int Q = x->Q;
+    for (long n = 0; n < N; ++n) {
+        double P = eos_pressure(x, rho[n]), P0 = rho[n] / 3.0;
+        x->psi[n] = sqrt(fabs(P - P0));
+        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
+    }
+    for (long n = 0; n < N; ++n) {
+        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
+            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
+            double wc = 3.0 * x->w[i] * (2.0 * rho[n1] - rho[n2]);
+            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
+        }
+        for (int a = 0; a < 3; ++a)
+            F[a * N + n] = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * rho[n] * Fc[a];
+    }
+}
+
+void orc_get_f(const void *h, double *out)
+{
+    const orc_ctx *x = (const orc_ctx *)h;
+    memcpy(out, x->f, sizeof(double) * (size_t)x->Q * x->N);
+}
+
+void orc_set_f(void *h, const double *in)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    memcpy(x->f, in, sizeof(double) * (size_t)x->Q * x->N);
+}

@@ -1,0 +1,359 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU. Each pin is chosen so that a plausible mistake
+in the oracle (a dropped term, a wrong sign or index, a transposed operand, a
+wrong weight) fails at least one of them:
+
+  lattice / product form   exact rational weights and isotropy (Sec. 2.3.2, eq wi)
+  equilibrium              closed-form moments incl. the D3Q27 third-moment bias
+  collision                mass, momentum + S, and the second-moment content of
+                           f* - f_eq required by the Chapman-Enskog solvability
+                           conditions (Appendix D)
+  Korteweg stencils        Taylor orders O(h^4) (pseudo-potential) and O(h^2)
+                           (capillary) against analytic derivatives (Sec. 2.3.4)
+  EOS / Maxwell            critical points, equal pressure and equal chemical
+                           potential from hand-derived closed forms, corresponding
+                           states (Sec. 3.1)
+  sigma                    near-critical van der Waals law (Sec. 3.2)
+  zero-force reduction     BGK shear-wave decay at nu = (1/omega - 1/2)/3 (Sec. 2.3.5)
+  full step                brute force against an independent NumPy step
+  invariants               exact mass, momentum change = sum of sources
+  physics                  thermodynamic convergence of coexistence to Maxwell
+                           with decreasing a (Sec. 3.1), Laplace's law (Sec. 3.2),
+                           force-sign reading (unstable / wrong with the literal sign)
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+from oracle import brute as B
+from oracle import oracle as O
+from oracle import thermo as T
+
+A9, B21 = 9.0 / 49.0, 2.0 / 21.0
+
+
+# ------------------------------------------------------------------ inputs
+def test_splitmix64_published_first_output():
+    # SplitMix64 with state 0: the first output is 0xE220A8397B1DCDAF (reference C code)
+    assert int(L.splitmix64(0, 1)[0]) == 0xE220A8397B1DCDAF
+
+
+# ------------------------------------------------------------------ lattice
+@pytest.mark.parametrize("D", [2, 3])
+def test_lattice_weights_exact(D):
+    c, w, opp = O.lattice(D)
+    nnz = np.count_nonzero(c[:, :D], axis=1)
+    expect = {2: {0: 4 / 9, 1: 1 / 9, 2: 1 / 36}, 3: {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}}[D]
+    for k, wk in expect.items():
+        np.testing.assert_allclose(w[nnz == k], wk, rtol=1e-15)
+    assert abs(w.sum() - 1.0) < 1e-15
+    for a in range(D):
+        for b in range(D):
+            m2 = (w * c[:, a] * c[:, b]).sum()
+            assert abs(m2 - (1 / 3 if a == b else 0)) < 1e-15
+            m4 = (w * c[:, a] ** 2 * c[:, b] ** 2).sum()
+            assert abs(m4 - (1 / 3 if a == b else 1 / 9)) < 1e-15
+    np.testing.assert_array_equal(c[opp], -c)
+
+
+# ------------------------------------------------------------------ equilibrium
+@pytest.mark.parametrize("D", [2, 3])
+def test_equilibrium_moments_closed_form(D):
+    c, w, _ = O.lattice(D)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        rho = rng.uniform(0.01, 10)
+        u = rng.uniform(-0.2, 0.2, 3)
+        u[D:] = 0
+        f = O.product_form(D, rho, u, 1 / 3 + u ** 2)
+        assert abs(f.sum() - rho) < 1e-14 * rho
+        for a in range(D):
+            assert abs((c[:, a] * f).sum() - rho * u[a]) < 1e-14 * rho
+            assert abs((c[:, a] ** 2 * f).sum() - rho * (1 / 3 + u[a] ** 2)) < 1e-14 * rho
+            # lattice bias c^3 = c: third diagonal moment equals rho u_a
+            assert abs((c[:, a] ** 3 * f).sum() - rho * u[a]) < 1e-14 * rho
+            for b in range(D):
+                if a != b:
+                    assert abs((c[:, a] * c[:, b] * f).sum() - rho * u[a] * u[b]) < 1e-14 * rho
+
+
+# ------------------------------------------------------------------ collision
+def _collision_check(D, variant):
+    c, w, _ = O.lattice(D)
+    cfg = O.Config(D, 4, 4, 4 if D == 3 else 1, variant=variant)
+    orc = O.Oracle(cfg)
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for _ in range(10):
+        rho0 = rng.uniform(0.5, 5)
+        u0 = rng.uniform(-0.1, 0.1, 3); u0[D:] = 0
+        f = O.product_form(D, rho0, u0, 1 / 3 + u0 ** 2) * (1 + rng.uniform(-0.05, 0.05, len(w)))
+        S = rng.uniform(-0.05, 0.05, 3); S[D:] = 0
+        Phi = rng.uniform(-0.01, 0.01, 3); Phi[D:] = 0
+        om = rng.uniform(0.6, 1.9)
+        fp = orc.collide(f, S, Phi, om)
+        rho = f.sum()
+        j = np.array([(c[:, a] * f).sum() for a in range(3)])
+        u = j / rho
+        assert abs(fp.sum() - rho) < 1e-14 * rho                     # mass
+        for a in range(D):                                           # momentum gains S
+            assert abs((c[:, a] * fp).sum() - (j[a] + S[a])) < 1e-14 * rho
+        feq = O.product_form(D, rho, u, 1 / 3 + u ** 2)
+        for a in range(D):
+            for b in range(D):
+                dst = ((c[:, a] * c[:, b]) * (fp - f - om * (feq - f))).sum()   # moment of f* - f_eq
+                want = u[a] * S[b] + S[a] * u[b] + S[a] * S[b] / rho + (Phi[a] if a == b else 0.0)
+                worst = max(worst, abs(dst - want))
+    return worst
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_collision_conservation_and_extended_equilibrium(D):
+    assert _collision_check(D, 0) < 1e-14
+
+
+def test_literal_zeta_reading_fails_the_solvability_pin():
+    # planted mistake (in the oracle, on the CPU): zeta* with u^2 instead of xi*^2
+    assert _collision_check(3, O.VARIANT_LITERAL_ZETA) > 1e-5
+
+
+# ------------------------------------------------------------------ Korteweg stencils
+def _sine_force_error(D, n, axis, eos, kappa):
+    amp, rho0 = 0.3, 3.0
+    nx, ny, nz = (n, 3, 3 if D == 3 else 1)
+    dims = [nx, ny, nz]
+    dims[0], dims[axis] = dims[axis], dims[0]
+    if D == 2 and axis == 2:
+        raise ValueError
+    nx, ny, nz = dims
+    cfg = O.Config(D, nx, ny, nz, eos, 0.02, B21, 1.0, 0.0, 0.9, kappa)
+    orc = O.Oracle(cfg)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = [x, y, z][axis].ravel().astype(float)
+    k = 2 * math.pi / n
+    rho = rho0 + amp * np.sin(k * s)
+    F = orc.korteweg_force(rho)[axis]
+    fl = cfg.fluid()
+    d1 = amp * k * np.cos(k * s)
+    d3 = -amp * k ** 3 * np.cos(k * s)
+    # F_K = grad(P - P0) - kappa rho grad lap rho (eq force_form, both branches)
+    exact = (fl.dpressure(rho) - 1 / 3) * d1 - kappa * rho * d3
+    return np.abs(F - exact).max() / np.abs(exact).max()
+
+
+@pytest.mark.parametrize("D,axis", [(2, 0), (2, 1), (3, 0), (3, 1), (3, 2)])
+def test_pseudopotential_stencil_is_fourth_order(D, axis):
+    # vdW at T_r = 0.9 with rho in [2.7, 3.3]: P < P0 everywhere, single sign branch
+    e1 = _sine_force_error(D, 24, axis, T.VDW, 0.0)
+    e2 = _sine_force_error(D, 48, axis, T.VDW, 0.0)
+    assert 13.0 < e1 / e2 < 19.0
+
+
+@pytest.mark.parametrize("D,axis", [(2, 0), (3, 2)])
+def test_capillary_stencil_is_second_order(D, axis):
+    e1 = _sine_force_error(D, 24, axis, T.IDEAL, 0.05)
+    e2 = _sine_force_error(D, 48, axis, T.IDEAL, 0.05)
+    assert 3.6 < e1 / e2 < 4.4
+
+
+# ------------------------------------------------------------------ EOS and Maxwell
+def test_vdw_critical_point():
+    fl = T.Fluid(T.VDW, A9, B21, 1.0)
+    rc = 1 / (3 * B21)
+    h = 1e-4
+    assert abs(fl.dpressure(rc)) < 1e-12
+    d2 = (fl.dpressure(rc + h) - fl.dpressure(rc - h)) / (2 * h)
+    assert abs(d2) < 1e-7
+    assert abs(fl.pressure(rc) - A9 / (27 * B21 ** 2)) < 1e-14
+
+
+@pytest.mark.parametrize("eos,om", [(T.PR, 0.344), (T.RKS, 0.344), (T.CS, 0.0)])
+def test_printed_critical_constants_are_near_inflection(eos, om):
+    # the printed a(Tc,Pc), b(Tc,Pc) constants are rounded, so dP/drho touches zero only approximately
+    fl = T.Fluid(eos, 0.05, B21, 1.0, 1.0, om)
+    r = np.linspace(0.05, 0.9 * fl.rho_max, 20001)
+    dmin = fl.dpressure(r).min()
+    assert abs(dmin) < 2e-3 * fl.R * fl.T
+
+
+@pytest.mark.parametrize("eos", [T.VDW, T.PR, T.RKS, T.CS])
+def test_oracle_c_eos_matches_thermo(eos):
+    cfg = O.Config(3, 2, 2, 2, eos, 0.03, B21, 1.0, 0.344, 0.7)
+    orc = O.Oracle(cfg)
+    fl = cfg.fluid()
+    assert abs(orc.temperature - fl.T) < 1e-16
+    for r in np.linspace(0.01, 0.95 * fl.rho_max, 37):
+        assert abs(orc.pressure(r) - float(fl.pressure(r))) <= 1e-14 * (1 + abs(float(fl.pressure(r))))
+
+
+def _mu_vdw(fl, r):
+    RT = fl.R * fl.T
+    return RT * math.log(r / (1 - fl.b * r)) + RT / (1 - fl.b * r) - 2 * fl.a * r
+
+
+def _mu_pr(fl, r):
+    RT, b, aa = fl.R * fl.T, fl.b, fl.a * fl.alpha
+    q = 1 + 2 * b * r - b * b * r * r
+    r1, r2 = (1 + math.sqrt(2)) / b, (1 - math.sqrt(2)) / b
+    att = aa * r / q + aa / (2 * math.sqrt(2) * b) * math.log(abs((r - r2) / (r - r1)))
+    return RT * math.log(r / (1 - b * r)) + RT / (1 - b * r) - att
+
+
+@pytest.mark.parametrize("tr", [0.5, 0.7, 0.9, 0.97])
+def test_maxwell_vdw_equal_pressure_and_chemical_potential(tr):
+    fl = T.Fluid(T.VDW, A9, B21, tr)
+    rv, rl, ps = T.coexistence(fl)
+    assert abs(float(fl.pressure(rv)) - ps) < 1e-12 * abs(ps) + 1e-15
+    assert abs(float(fl.pressure(rl)) - ps) < 1e-12 * abs(ps) + 1e-15
+    assert abs(_mu_vdw(fl, rv) - _mu_vdw(fl, rl)) < 1e-11 * abs(_mu_vdw(fl, rl))
+
+
+@pytest.mark.parametrize("tr", [0.5, 0.6, 0.8])
+def test_maxwell_pr_equal_chemical_potential(tr):
+    fl = T.Fluid(T.PR, 2 / 49, B21, tr, 1.0, 0.344)
+    rv, rl, ps = T.coexistence(fl)
+    assert abs(_mu_pr(fl, rv) - _mu_pr(fl, rl)) < 1e-10 * abs(_mu_pr(fl, rl))
+
+
+def test_corresponding_states_and_critical_limit():
+    r1 = T.coexistence(T.Fluid(T.VDW, A9, B21, 0.8))
+    r2 = T.coexistence(T.Fluid(T.VDW, 0.0013, B21, 0.8))
+    assert abs(r1[1] / r1[0] - r2[1] / r2[0]) < 1e-9 * r1[1] / r1[0]
+    rv, rl, _ = T.coexistence(T.Fluid(T.VDW, A9, B21, 0.9999))
+    rc = 1 / (3 * B21)
+    assert abs(rv - rc) / rc < 0.03 and abs(rl - rc) / rc < 0.03
+
+
+def test_sigma_approaches_near_critical_vdw_law():
+    ratios = []
+    for tr in (0.97, 0.99, 0.995):
+        fl = T.Fluid(T.VDW, A9, B21, tr)
+        ratios.append(T.surface_tension(fl, 0.01) / T.vdw_sigma_near_critical(fl, 0.01))
+    assert ratios[0] < ratios[1] < ratios[2] < 1.0
+    assert ratios[2] > 0.995
+    fl = T.Fluid(T.VDW, A9, B21, 0.9)
+    assert abs(T.surface_tension(fl, 0.04) / T.surface_tension(fl, 0.01) - 2.0) < 1e-7   # sigma ~ sqrt(kappa)
+
+
+def test_kappa_for_width_roundtrip():
+    fl = T.Fluid(T.PR, 2 / 49, B21, 0.6, 1.0, 0.344)
+    k = T.kappa_for_width(fl, 5.0)
+    assert abs(T.interface_width(fl, k) - 5.0) < 1e-9
+
+
+# ------------------------------------------------------------------ zero-force reduction
+def test_ideal_gas_shear_wave_decays_at_bgk_viscosity():
+    n, tau, amp = 64, 0.8, 1e-4
+    cfg = O.Config(2, n, 2, 1, T.IDEAL, 0.0, 0.0, 1.0, 0.0, 1.0, 0.0, tau)
+    orc = O.Oracle(cfg)
+    x = np.tile(np.arange(n), 2).astype(float)
+    u = np.zeros((2, 2 * n))
+    u[1] = amp * np.sin(2 * math.pi * x / n)
+    orc.init(np.ones(2 * n), u)
+    steps = 2000
+    orc.step(steps)
+    _, U, _ = orc.moments()
+    a_sim = 2 / (2 * n) * (U[1] * np.sin(2 * math.pi * x / n)).sum()
+    nu = (tau - 0.5) / 3
+    k = 2 * math.pi / n
+    rate = -math.log(a_sim / amp) / steps
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+# ------------------------------------------------------------------ brute force
+CASES = [
+    (2, (1, 5, 6), T.VDW, 0.02, 0.0, False),
+    (2, (1, 7, 5), T.CS, 0.02, 0.0, True),
+    (3, (4, 5, 6), T.PR, 0.005, 0.344, False),
+    (3, (5, 4, 6), T.RKS, 0.01, 0.3, True),
+    (3, (3, 3, 3), T.VDW, 0.02, 0.0, True),
+]
+
+
+@pytest.mark.parametrize("D,zyx,eos,a,om,masked", CASES)
+def test_oracle_matches_independent_numpy_step(D, zyx, eos, a, om, masked):
+    nz, ny, nx = zyx
+    fl = T.Fluid(eos, a, B21, 0.7, 1.0, om)
+    rv, rl, _ = T.coexistence(fl)
+    N = nx * ny * nz
+    rho, u = L.random_state(N, D, rv, rl, 0.05, 11)
+    mask = L.random_mask(nx, ny, nz, 0.15, 3) if masked else None
+    tv = 0.6 if masked else 0.0
+    cfg = O.Config(D, nx, ny, nz, eos, a, B21, 1.0, om, 0.7, 0.02, 0.8, tv, rl, rv, rho_wall=rv)
+    r1, U1, _ = O.Oracle(cfg, mask).init(rho, u).step(10).moments()
+    shape = (ny, nx) if D == 2 else (nz, ny, nx)
+    bf = B.BruteForce(D, shape, fl, 0.02, 0.8, rho_wall=rv, mask=mask, tau_vapour=tv, rho_liquid=rl, rho_vapour=rv)
+    r2, U2 = bf.init(rho, u).step(10).moments()
+    assert np.abs(r1 - r2).max() < 1e-13 * np.abs(r2).max()
+    assert np.abs(U1 - U2).max() < 1e-13
+
+
+# ------------------------------------------------------------------ invariants
+@pytest.mark.parametrize("D,masked", [(2, False), (3, False), (3, True)])
+def test_mass_exact_and_momentum_changes_by_source(D, masked):
+    nx, ny, nz = (12, 10, 8) if D == 3 else (24, 20, 1)
+    fl = T.Fluid(T.PR, 0.005, B21, 0.6, 1.0, 0.344)
+    rv, rl, _ = T.coexistence(fl)
+    rho, u = L.random_state(nx * ny * nz, D, rv, 0.5 * rl, 0.03, 5)
+    mask = L.random_mask(nx, ny, nz, 0.1, 9) if masked else None
+    cfg = O.Config(D, nx, ny, nz, T.PR, 0.005, B21, 1.0, 0.344, 0.6, 0.02, 0.7, rho_wall=rv)
+    orc = O.Oracle(cfg, mask).init(rho, u)
+    _, _, t0 = orc.moments()
+    S = orc.source()
+    orc.step(1)
+    _, _, t1 = orc.moments()
+    assert abs(t1[0] - t0[0]) < 1e-13 * t0[0]
+    if not masked:
+        for a in range(D):
+            assert abs((t1[1 + a] - t0[1 + a]) - S[a].sum()) < 1e-12 * t0[0]
+
+
+# ------------------------------------------------------------------ physics
+def _flat_errors(a, tr=0.8, kappa=0.02, steps=12000, variant=0):
+    fl = T.Fluid(T.VDW, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    W = T.interface_width(fl, kappa)
+    n = int(max(64, 20 * W)); n += n % 2
+    cfg = O.Config(2, n, 1, 1, T.VDW, a, B21, 1.0, 0.0, tr, kappa, 0.8, variant=variant)
+    r, U, _ = O.Oracle(cfg).init(L.flat_slab(n, 1, 1, rl, rv, W)).step(steps).moments()
+    return (r[n // 2] - rl) / rl, (r[0] - rv) / rv, np.abs(U).max()
+
+
+def test_coexistence_converges_to_maxwell_as_a_decreases():
+    el1, ev1, _ = _flat_errors(0.04)
+    el2, ev2, _ = _flat_errors(0.005)
+    assert abs(ev1) < 0.02 and abs(el1) < 2e-3
+    assert abs(ev2) < abs(ev1) / 3
+    assert abs(el2) < 1e-3
+
+
+def test_literal_force_sign_is_unphysical():
+    # planted mistake: S = +F drives the interface away from Maxwell's densities (or diverges)
+    el, ev, um = _flat_errors(0.04, steps=3000, variant=O.VARIANT_LITERAL_FORCE_SIGN)
+    assert not (np.isfinite(ev) and abs(ev) < 0.05 and abs(el) < 0.05)
+
+
+@pytest.mark.slow
+def test_laplace_law_static_drops():
+    a, tr, kappa, n = 0.04, 0.8, 0.02, 96
+    fl = T.Fluid(T.VDW, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    W = T.interface_width(fl, kappa)
+    sigma = T.surface_tension(fl, kappa)
+    cfg = O.Config(2, n, n, 1, T.VDW, a, B21, 1.0, 0.0, tr, kappa, 0.8)
+    pts = []
+    for R in (12, 18, 27):
+        r, _, _ = O.Oracle(cfg).init(L.drop(n, n, 1, R, rl, rv, W)).step(6000).moments()
+        r2 = r.reshape(n, n)
+        rin = r2[n // 2 - 1:n // 2 + 1, n // 2 - 1:n // 2 + 1].mean()
+        rout = r2[0, 0]
+        Re = T.equimolar_radius_2d(r, rout, rin)
+        pts.append((1 / Re, float(fl.pressure(rin) - fl.pressure(rout))))
+    x, y = np.array(pts).T
+    slope, icpt = np.polyfit(x, y, 1)
+    assert np.std(y / x) / np.mean(y / x) < 0.01        # Delta P * R_e constant
+    assert abs(icpt) < 0.02 * y.max()
+    assert 0.8 < slope / sigma < 1.25                   # W = 3: not yet thermodynamically converged
