@@ -1,0 +1,154 @@
+/*
+ * lbm2p.h -- C ABI of the MI355X (gfx950) two-phase lattice Boltzmann library.
+ *
+ * The library advances the lattice BGK model of Hosseini, Dorschner & Karlin,
+ * "Towards a consistent lattice Boltzmann model for two-phase fluid", Sec. 2.3:
+ * populations on the D2Q9 or D3Q27 lattice (eq d3q27vel; D2Q9 drops z), a
+ * non-ideal equation of state entering through the pseudo-potential and the
+ * capillary Korteweg force on two neighbour rings (eq Kforce_final), the
+ * product-form equilibrium and extended equilibrium (eqs LBMeq, LBMstar) with
+ * the diagonal correction (eq correction), and the LBGK update (eq LBGK).
+ *
+ * Conventions for every entry point:
+ *   - return LBM_OK (0) on success or a negative LBM_E_* code; the message is
+ *     available from lbm_last_error();
+ *   - host arrays are owned by the caller and only read or written during the
+ *     call; all host fields are FP64 whatever the storage precision;
+ *   - node index n = x + nx*(y + ny*z), x fastest; vector fields are SoA [D][N];
+ *   - a context owns all of its device memory and one HIP stream; it is bound
+ *     to the device that was current at lbm_create and must be used from one
+ *     host thread at a time; different contexts are independent;
+ *   - errors raised by the watchdog (LBM_E_DIVERGED, LBM_E_DOMAIN) are sticky
+ *     until the next successful lbm_init_fields / lbm_set_populations.
+ */
+#ifndef LBM2P_H
+#define LBM2P_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_E_INVAL (-1)    /* bad argument or parameter */
+#define LBM_E_NOMEM (-2)    /* device or host allocation failed */
+#define LBM_E_HIP (-3)      /* a HIP runtime call failed */
+#define LBM_E_DOMAIN (-4)   /* rho <= 0, b*rho >= 1 (outside the EOS domain) or no van der Waals loop */
+#define LBM_E_DIVERGED (-5) /* non-finite mass or momentum at a watchdog check */
+#define LBM_E_STATE (-6)    /* call out of order (e.g. step before init) */
+
+enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
+/* Equations of state of Sec. 3.1: van der Waals (eq vdWEoS), Peng-Robinson
+ * (eq PREoS), Redlich-Kwong-Soave (eq RKSEoS), Carnahan-Starling (eq CSEos);
+ * LBM_EOS_IDEAL is P = rho/3 = P0, i.e. no non-ideal force (plain LBGK). */
+enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_RKS = 2, LBM_EOS_CS = 3, LBM_EOS_IDEAL = 4 };
+/* LBM_FP64: populations stored and updated in FP64.
+ * LBM_FP32_DEV: populations stored as FP32 deviations h_i = f_i - w_i rho_ref and
+ * updated in FP32; mass and momentum reductions stay FP64. */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+
+/* Problem statement (Sec. 2.3 and Sec. 3.1). Units: lattice units, dr = dt = 1. */
+typedef struct {
+    int lattice;            /* LBM_D2Q9 or LBM_D3Q27 */
+    int nx, ny, nz;         /* grid; periodic on every axis; nz must be 1 for D2Q9 */
+    int eos;                /* LBM_EOS_* */
+    double a, b, R;         /* EOS attraction, co-volume, gas constant */
+    double acentric;        /* acentric factor omega' of PR / RKS */
+    double T_reduced;       /* T/Tc; Tc from the printed a(Tc,Pc), b(Tc,Pc) relations */
+    double kappa;           /* capillary coefficient kappa~ of eq capillary_discrete */
+    double tau_liquid;      /* relaxation time, omega = 1/tau; viscosity (tau - 1/2)/3 */
+    double tau_vapour;      /* > 0: kinematic viscosity linear in rho between the two
+                               bulk densities below (clamped); <= 0: constant tau_liquid */
+    double rho_liquid, rho_vapour; /* bulk densities for the viscosity interpolation */
+    double rho_wall;        /* virtual density of solid nodes (wetting, Sec. 4.5) */
+    const uint8_t *mask;    /* nullable host array [N], 1 = solid; copied at create */
+    int precision;          /* LBM_FP64 or LBM_FP32_DEV */
+    double rho_ref;         /* reference density of the FP32 deviation storage */
+    int check_every;        /* watchdog period in steps inside lbm_step: > 0 every
+                               check_every steps and at the end, 0 at the end only,
+                               < 0 never */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+/* Allocates a context for one simulation (Sec. 2.3). Validates p (lattice, sizes,
+ * tau > 1/2, kappa >= 0, EOS parameters, 0 < T_reduced for non-ideal EOS),
+ * derives T = T_reduced * Tc (Sec. 3.1), allocates two population lattices in
+ * device memory and uploads the mask. *out receives the context; on failure *out
+ * is NULL and the message is available from lbm_last_error(NULL). */
+int lbm_create(const lbm_params *p, lbm_ctx **out);
+
+/* Sets f_i = f_i^eq(rho, u) (eq LBMeq) at every fluid node. rho: host [N],
+ * u: host [D][N] or NULL for rest. Records the initial mass and momentum and
+ * clears sticky errors. Synchronous. */
+int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u);
+
+/* Advances n time steps of eq LBGK (stream-collide with the Korteweg force and
+ * halfway bounce-back at solid nodes). Runs the FP64 watchdog as selected by
+ * check_every; returns LBM_E_DIVERGED / LBM_E_DOMAIN when it trips. When no
+ * check runs, the call only enqueues work on the context stream. */
+int lbm_step(lbm_ctx *c, int64_t n);
+
+/* Density and velocity of the current state. rho: host [N] (nullable); U: host
+ * [D][N] (nullable), the velocity U = u + S/(2 rho) shifted by half the force
+ * increment (Sec. 2.3.5, Appendix D); solid nodes report rho_wall and U = 0.
+ * totals: host [4] (nullable) = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z}
+ * over fluid nodes with the unshifted u, reduced in FP64 in a fixed order.
+ * Synchronous. */
+int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]);
+
+/* Releases all device memory and the stream. NULL-safe. */
+void lbm_destroy(lbm_ctx *c);
+
+/* Last error message of c, or of the calling thread's last lbm_create /
+ * lbm_batch_create when c is NULL. Never NULL; valid until the next call. */
+const char *lbm_last_error(const lbm_ctx *c);
+
+/* Makes the context enqueue its work on hip_stream (a hipStream_t, not owned);
+ * NULL restores the context's own stream. */
+int lbm_set_stream(lbm_ctx *c, void *hip_stream);
+
+/* Checkpoint: copies the population lattice to / from a host buffer of
+ * lbm_population_bytes(c) bytes in storage precision (FP64 f_i or FP32 h_i).
+ * The layout is the library's own and opaque; a set of what get returned
+ * resumes bit-exactly. Synchronous. */
+int64_t lbm_population_bytes(const lbm_ctx *c);
+int lbm_get_populations(lbm_ctx *c, void *host);
+int lbm_set_populations(lbm_ctx *c, const void *host);
+
+/* Runs n steps with HIP events around every kernel launch on the context
+ * stream and returns the summed device time per kernel kind in ms:
+ * ms[0] = moment pass, ms[1] = collide-stream pass (or the fused step kernel),
+ * ms[2] = everything in the step loop. launches[0..1] = number of launches.
+ * A measurement mode for the bench; the state advances exactly as lbm_step. */
+int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]);
+
+/* Thermodynamics of the problem statement, host only (Sec. 3.1). out[0] = rho_v,
+ * out[1] = rho_l, out[2] = P_sat from the Maxwell equal-area rule
+ * (eq Maxwell_equal_area), out[3] = T = T_reduced * Tc. Returns LBM_E_DOMAIN
+ * when the EOS has no van der Waals loop at that temperature. */
+int lbm_coexistence(const lbm_params *p, double out[4]);
+
+/* Capillary coefficient for which the flat equilibrium interface of the
+ * second-gradient fluid (Sec. 2.1) has width W = (rho_l - rho_v)/max|grad rho|
+ * (eq interface_W). Host only. */
+int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa);
+
+/* Batched sweep: ncases independent simulations (each a full lbm_params,
+ * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes) advanced by ONE persistent
+ * kernel launch per lbm_batch_step call, captured in a HIP graph; each case is
+ * owned by one workgroup that runs the whole step loop with workgroup barriers.
+ * Tile shapes and workgroup sizes come from the built-in autotuner. */
+int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out);
+int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const double *u);
+int lbm_batch_step(lbm_batch *b, int64_t n);
+int lbm_batch_moments(lbm_batch *b, int icase, double *rho, double *U, double totals[4]);
+void lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM2P_H */

@@ -1,0 +1,57 @@
+// kernels.hpp -- host-side view of the step kernels (launch wrappers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+// grid geometry; N < 2^31; qs = element stride between the Q population arrays
+struct Geom {
+    int nx, ny, nz;
+    int N;
+    long long qs;
+};
+
+// per-simulation constants of the step in compute precision C
+template <class C> struct Params {
+    C rho_ref;      // deviation-storage reference density (0 for plain FP64 storage)
+    C rho_w;        // virtual wall density
+    C kappa;        // capillary coefficient
+    C omega_l;      // 1/tau_liquid
+    C nu_l, nu_v;   // kinematic viscosities of the bulk phases (variable-viscosity mode)
+    C rho_l, rho_v; // bulk densities of the viscosity interpolation
+    int var_visc;
+    Eos<C> eos;
+};
+
+// number of reduction slots written per workgroup by the moment pass
+constexpr int kPartialSlots = 5;   // sum rho, sum j_x, j_y, j_z, domain-error count
+
+// one table of launchers per (lattice, precision, mask) combination
+struct KernelSet {
+    // zero the population array (fill kernel, safe under graph capture)
+    void (*fill_zero)(hipStream_t, void *A, long long count);
+    // f = f_eq(rho0, u0), written in pull layout with bounce-back links folded in
+    void (*init)(hipStream_t, void *A, const Geom &, const uint8_t *mask, const void *params,
+                 const double *rho0, const double *u0);
+    // rho and g = rho u^3 of the current state, per-workgroup FP64 partials
+    void (*moments)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
+                    void *rho, void *g, double *partials);
+    // one collide-stream step A -> B (reads rho, g written by moments)
+    void (*collide)(hipStream_t, const void *A, void *B, const Geom &, const uint8_t *mask, const void *params,
+                    const void *rho, const void *g);
+    // rho and U = u + S/(2 rho) of the current state in FP64 (reads rho, g)
+    void (*output)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
+                   const void *rho, const void *g, double *out_rho, double *out_U);
+    int moment_blocks;  // filled by kernel_blocks()
+};
+
+KernelSet kernel_set(int D, bool fp64, bool masked);
+int moment_block_count(int D, const Geom &g);
+
+// deterministic FP64 tree over nblocks partial rows -> totals[0..4]
+void launch_reduce(hipStream_t s, const double *partials, int nblocks, double *totals);
+
+}  // namespace lbm

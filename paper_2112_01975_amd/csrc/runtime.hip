@@ -1,0 +1,310 @@
+// runtime.hip -- C ABI of the single-simulation path: parameter validation,
+// device memory, the step loop, the FP64 watchdog, moments output, checkpoints.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/lbm2p.h"
+#include "kernels.hpp"
+#include "runtime_common.hpp"
+#include "thermo_host.hpp"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    lbm_params p;
+    int D = 0, Q = 0;
+    bool fp64 = true, masked = false;
+    Geom g{};
+    int device = 0;
+    size_t sbytes = 8;               // bytes per stored population
+    hipStream_t own = nullptr, stream = nullptr;
+    void *A = nullptr, *B = nullptr; // population lattices
+    void *rho = nullptr, *gfl = nullptr;
+    uint8_t *mask = nullptr;
+    double *partials = nullptr, *totals = nullptr;
+    double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
+    int nblk = 0;
+    Params<double> pd{};
+    Params<float> pf{};
+    KernelSet ks{};
+    bool initialized = false;
+    int sticky = 0;
+    double M0 = 0.0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(lbm_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg; else g_create_err = msg;
+    return code;
+}
+
+#define HIP_OR_FAIL(c, call)                                                                  \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((c), LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd : (const void *)&c->pf; }
+
+void free_ctx(lbm_ctx *c) {
+    if (!c) return;
+    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->partials, c->totals, c->io};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+}
+
+// mass/momentum of the current state -> host[5]; also the domain-error count
+int reduce_state(lbm_ctx *c, double host[5]) {
+    c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+    launch_reduce(c->stream, c->partials, c->nblk, c->totals);
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipMemcpyAsync(host, c->totals, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int watchdog(lbm_ctx *c) {
+    double t[5];
+    int rc = reduce_state(c, t);
+    if (rc) return rc;
+    if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) || !isfinite(t[3])) {
+        c->sticky = LBM_E_DIVERGED;
+        return fail(c, LBM_E_DIVERGED, "non-finite mass or momentum (simulation diverged)");
+    }
+    if (t[4] > 0.0) {
+        c->sticky = LBM_E_DOMAIN;
+        return fail(c, LBM_E_DOMAIN, "density left the EOS domain (rho <= 0 or b*rho >= 1) at " +
+                                         std::to_string((long long)t[4]) + " nodes");
+    }
+    return LBM_OK;
+}
+
+int one_step(lbm_ctx *c) {
+    c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+    c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+    void *t = c->A; c->A = c->B; c->B = t;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create(const lbm_params *p, lbm_ctx **out) {
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!validate_params(p, &why)) return fail(nullptr, LBM_E_INVAL, why);
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    c->p.mask = nullptr;
+    c->D = p->lattice == LBM_D3Q27 ? 3 : 2;
+    c->Q = c->D == 3 ? 27 : 9;
+    c->fp64 = p->precision == LBM_FP64;
+    c->masked = p->mask != nullptr;
+    c->sbytes = c->fp64 ? 8 : 4;
+    c->g = make_geom(p->nx, p->ny, c->D == 3 ? p->nz : 1);
+    fill_params(p, &c->pd);
+    fill_params(p, &c->pf);
+    c->ks = kernel_set(c->D, c->fp64, c->masked);
+    c->nblk = moment_block_count(c->D, c->g);
+    const size_t N = (size_t)c->g.N;
+    const size_t cbytes = c->fp64 ? 8 : 4;
+    hipError_t e;
+    if ((e = hipGetDevice(&c->device)) != hipSuccess || (e = hipStreamCreate(&c->own)) != hipSuccess) {
+        free_ctx(c);
+        return fail(nullptr, LBM_E_HIP, std::string("HIP initialisation failed: ") + hipGetErrorString(e));
+    }
+    c->stream = c->own;
+    const size_t pop = (size_t)c->Q * (size_t)c->g.qs * c->sbytes;
+    if (hipMalloc(&c->A, pop) != hipSuccess || hipMalloc(&c->B, pop) != hipSuccess ||
+        hipMalloc(&c->rho, N * cbytes) != hipSuccess || hipMalloc(&c->gfl, (size_t)c->D * N * cbytes) != hipSuccess ||
+        hipMalloc((void **)&c->partials, (size_t)c->nblk * kPartialSlots * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->totals, 8 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->io, (size_t)(1 + c->D) * N * sizeof(double)) != hipSuccess) {
+        free_ctx(c);
+        return fail(nullptr, LBM_E_NOMEM, "device allocation failed (" + std::to_string(2 * pop >> 20) + " MiB of populations)");
+    }
+    if (c->masked) {
+        if (hipMalloc((void **)&c->mask, N) != hipSuccess) {
+            free_ctx(c);
+            return fail(nullptr, LBM_E_NOMEM, "device allocation of the mask failed");
+        }
+        if ((e = hipMemcpy(c->mask, p->mask, N, hipMemcpyHostToDevice)) != hipSuccess) {
+            free_ctx(c);
+            return fail(nullptr, LBM_E_HIP, std::string("mask upload failed: ") + hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u) {
+    if (!c || !rho) return fail(c, LBM_E_INVAL, "context or rho is NULL");
+    const size_t N = (size_t)c->g.N;
+    for (size_t n = 0; n < N; ++n) {
+        if (!(rho[n] > 0.0) || !isfinite(rho[n])) return fail(c, LBM_E_DOMAIN, "initial density must be finite and > 0");
+    }
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->io, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (u) HIP_OR_FAIL(c, hipMemcpyAsync(c->io + N, u, (size_t)c->D * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const long long count = (long long)c->Q * c->g.qs;
+    c->ks.fill_zero(c->stream, c->A, count);
+    c->ks.fill_zero(c->stream, c->B, count);
+    c->ks.init(c->stream, c->A, c->g, c->mask, params_ptr(c), c->io, u ? c->io + N : nullptr);
+    HIP_OR_FAIL(c, hipGetLastError());
+    c->sticky = 0;
+    c->initialized = true;
+    double t[5];
+    int rc = reduce_state(c, t);
+    if (rc) return rc;
+    c->M0 = t[0];
+    return watchdog(c);
+}
+
+int lbm_step(lbm_ctx *c, int64_t n) {
+    if (!c) return fail(c, LBM_E_INVAL, "context is NULL");
+    if (n < 0) return fail(c, LBM_E_INVAL, "negative step count");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_step before lbm_init_fields");
+    if (c->sticky) return c->sticky;
+    const int ce = c->p.check_every;
+    for (int64_t t = 0; t < n; ++t) {
+        one_step(c);
+        if (ce > 0 && (t + 1) % ce == 0 && t + 1 < n) {
+            int rc = watchdog(c);
+            if (rc) return rc;
+        }
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    if (ce >= 0) return watchdog(c);
+    return LBM_OK;
+}
+
+int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
+    if (!c || !ms || !launches) return fail(c, LBM_E_INVAL, "NULL argument");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_step_timed before lbm_init_fields");
+    if (c->sticky) return c->sticky;
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIP_OR_FAIL(c, hipEventCreate(&e));
+    hipEvent_t tot0, tot1;
+    HIP_OR_FAIL(c, hipEventCreate(&tot0));
+    HIP_OR_FAIL(c, hipEventCreate(&tot1));
+    double acc[2] = {0.0, 0.0};
+    HIP_OR_FAIL(c, hipEventRecord(tot0, c->stream));
+    for (int64_t t = 0; t < n; ++t) {
+        HIP_OR_FAIL(c, hipEventRecord(ev[0], c->stream));
+        c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+        HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
+        c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
+        HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        HIP_OR_FAIL(c, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIP_OR_FAIL(c, hipEventElapsedTime(&b, ev[1], ev[2]));
+        acc[0] += a;
+        acc[1] += b;
+        void *tmp = c->A; c->A = c->B; c->B = tmp;
+    }
+    HIP_OR_FAIL(c, hipEventRecord(tot1, c->stream));
+    HIP_OR_FAIL(c, hipEventSynchronize(tot1));
+    float tt = 0.f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&tt, tot0, tot1));
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(tot0);
+    (void)hipEventDestroy(tot1);
+    ms[0] = acc[0];
+    ms[1] = acc[1];
+    ms[2] = tt;
+    launches[0] = n;
+    launches[1] = n;
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]) {
+    if (!c) return fail(c, LBM_E_INVAL, "context is NULL");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_moments before lbm_init_fields");
+    double t[5];
+    int rc = reduce_state(c, t);    // also refreshes rho and g of the current state
+    if (rc) return rc;
+    if (totals) for (int k = 0; k < 4; ++k) totals[k] = t[k];
+    if (rho || U) {
+        const size_t N = (size_t)c->g.N;
+        c->ks.output(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->io, c->io + N);
+        HIP_OR_FAIL(c, hipGetLastError());
+        if (rho) HIP_OR_FAIL(c, hipMemcpyAsync(rho, c->io, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (U) HIP_OR_FAIL(c, hipMemcpyAsync(U, c->io + N, (size_t)c->D * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int lbm_set_stream(lbm_ctx *c, void *hip_stream) {
+    if (!c) return fail(c, LBM_E_INVAL, "context is NULL");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own;
+    return LBM_OK;
+}
+
+int64_t lbm_population_bytes(const lbm_ctx *c) {
+    return c ? (int64_t)c->Q * (int64_t)c->g.N * (int64_t)c->sbytes : 0;
+}
+
+int lbm_get_populations(lbm_ctx *c, void *host) {
+    if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "no state to checkpoint");
+    const size_t row = (size_t)c->g.N * c->sbytes;
+    for (int i = 0; i < c->Q; ++i)
+        HIP_OR_FAIL(c, hipMemcpyAsync((char *)host + i * row, (char *)c->A + (size_t)i * c->g.qs * c->sbytes, row,
+                                      hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, const void *host) {
+    if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
+    const size_t row = (size_t)c->g.N * c->sbytes;
+    for (int i = 0; i < c->Q; ++i)
+        HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->A + (size_t)i * c->g.qs * c->sbytes, (const char *)host + i * row, row,
+                                      hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->initialized = true;
+    c->sticky = 0;
+    return watchdog(c);
+}
+
+int lbm_coexistence(const lbm_params *p, double out[4]) {
+    if (!p || !out) return fail(nullptr, LBM_E_INVAL, "NULL argument");
+    HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
+    double rv, rl, ps;
+    if (coexistence(e, &rv, &rl, &ps)) return fail(nullptr, LBM_E_DOMAIN, "no van der Waals loop at this temperature");
+    out[0] = rv; out[1] = rl; out[2] = ps; out[3] = e.T;
+    return LBM_OK;
+}
+
+int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa) {
+    if (!p || !kappa || !(width > 0)) return fail(nullptr, LBM_E_INVAL, "bad argument");
+    HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
+    if (kappa_for_width(e, width, kappa)) return fail(nullptr, LBM_E_DOMAIN, "no van der Waals loop at this temperature");
+    return LBM_OK;
+}
+
+}  // extern "C"

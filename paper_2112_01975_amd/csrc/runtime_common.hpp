@@ -1,0 +1,69 @@
+// runtime_common.hpp -- parameter checks and derived constants shared by the
+// single-simulation and batched runtimes.
+#pragma once
+#include <math.h>
+
+#include <string>
+
+#include "../../include/lbm2p.h"
+#include "kernels.hpp"
+#include "thermo_host.hpp"
+
+namespace lbm {
+
+// Element stride between population arrays: N rounded up to a 256 B multiple plus
+// a 768 B (FP32) skew so that the Q arrays do not start on the same HBM channel.
+inline Geom make_geom(int nx, int ny, int nz) {
+    Geom g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.N = nx * ny * nz;
+    g.qs = (((long long)g.N + 63) / 64) * 64 + 192;
+    return g;
+}
+
+inline bool validate_params(const lbm_params *p, std::string *why) {
+    if (!p) { *why = "params is NULL"; return false; }
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27) { *why = "lattice must be LBM_D2Q9 or LBM_D3Q27"; return false; }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { *why = "grid sizes must be >= 1"; return false; }
+    if (p->lattice == LBM_D2Q9 && p->nz != 1) { *why = "D2Q9 requires nz == 1"; return false; }
+    if ((double)p->nx * p->ny * p->nz >= 2147483647.0) { *why = "grid larger than 2^31 nodes"; return false; }
+    if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_IDEAL) { *why = "unknown equation of state"; return false; }
+    if (p->eos != LBM_EOS_IDEAL) {
+        if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0)) { *why = "EOS parameters a, b, R must be > 0"; return false; }
+        if (!(p->T_reduced > 0)) { *why = "T_reduced must be > 0"; return false; }
+    }
+    if (!(p->kappa >= 0) || !isfinite(p->kappa)) { *why = "kappa must be finite and >= 0"; return false; }
+    if (!(p->tau_liquid > 0.5) || !isfinite(p->tau_liquid)) { *why = "tau_liquid must be > 1/2"; return false; }
+    if (p->tau_vapour > 0) {
+        if (!(p->tau_vapour > 0.5)) { *why = "tau_vapour must be > 1/2 (or <= 0 for constant tau)"; return false; }
+        if (!(p->rho_liquid > p->rho_vapour) || !(p->rho_vapour >= 0)) {
+            *why = "variable viscosity needs rho_liquid > rho_vapour >= 0";
+            return false;
+        }
+    }
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32_DEV) { *why = "unknown precision"; return false; }
+    if (!isfinite(p->rho_ref) || !isfinite(p->rho_wall)) { *why = "rho_ref and rho_wall must be finite"; return false; }
+    if (p->mask && !(p->rho_wall > 0)) { *why = "a mask needs rho_wall > 0"; return false; }
+    return true;
+}
+
+template <class C> inline void fill_params(const lbm_params *p, Params<C> *q) {
+    HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
+    q->rho_ref = C(p->rho_ref);
+    q->rho_w = C(p->rho_wall);
+    q->kappa = C(p->kappa);
+    q->omega_l = C(1.0 / p->tau_liquid);
+    q->var_visc = p->tau_vapour > 0 ? 1 : 0;
+    q->nu_l = C((p->tau_liquid - 0.5) / 3.0);
+    q->nu_v = C(p->tau_vapour > 0 ? (p->tau_vapour - 0.5) / 3.0 : 0.0);
+    q->rho_l = C(p->rho_liquid);
+    q->rho_v = C(p->rho_vapour);
+    q->eos.kind = p->eos;
+    q->eos.RT = C(p->R * e.T);
+    q->eos.aa = C(e.aa);
+    q->eos.b = C(p->b);
+}
+
+}  // namespace lbm

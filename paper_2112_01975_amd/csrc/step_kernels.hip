@@ -1,0 +1,430 @@
+// step_kernels.hip -- two-pass stream-collide step of the two-phase LBGK model
+// (Sec. 2.3) for gfx950.
+//
+// Storage: structure of arrays A[i*qs + n], n = x + nx*(y + ny*z). The array holds
+// post-collision populations at the node that produced them; every pass pulls
+// f_i(r) = A_i(r - c_i), or A_opp(i)(r) when r - c_i is solid (halfway bounce-back).
+//
+// Pass 1 (moments): rho = rho_ref + sum h_i, j = sum c_i h_i, g_a = rho u_a^3; FP64
+//   per-workgroup partial sums of mass and momentum for the watchdog.
+// Pass 2 (collide): stages rho and the signed pseudo-potential of a 64x4xZB tile
+//   plus a two-node halo in LDS, evaluates the two-ring Korteweg force
+//   (eq Kforce_final), the diagonal correction Phi (eq correction), the product-form
+//   equilibrium and extended equilibrium (eqs LBMeq, LBMstar) in cancellation-free
+//   deviation form, and the LBGK update (eq LBGK).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+namespace {
+
+constexpr int TX = 64;   // tile width in x: one wave64 row, coalesced 256 B (FP32) loads
+constexpr int TY = 4;    // tile height in y: 4 waves per workgroup
+constexpr int HALO = 2;  // two neighbour rings
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    if ((unsigned)v < (unsigned)n) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <class C> __device__ __forceinline__ C omega_of(const Params<C> &p, C rho) {
+    if (!p.var_visc) return p.omega_l;
+    C s = (rho - p.rho_v) / (p.rho_l - p.rho_v);
+    s = s < C(0) ? C(0) : (s > C(1) ? C(1) : s);
+    C nu = p.nu_v + (p.nu_l - p.nu_v) * s;
+    return C(1) / (C(3) * nu + C(0.5));
+}
+
+// wrapped neighbour coordinates of (x, y, z): xs[k] = x + k - 1, ro[j][l] = row offset of (y + j - 1, z + l - 1)
+template <int D> struct Nbr {
+    int xs[3];
+    int ro[3][3];
+    __device__ __forceinline__ Nbr(const Geom &g, int x, int y, int z) {
+        xs[0] = wrapi(x - 1, g.nx); xs[1] = x; xs[2] = wrapi(x + 1, g.nx);
+        int ys[3] = {wrapi(y - 1, g.ny), y, wrapi(y + 1, g.ny)};
+        if constexpr (D == 3) {
+            int zs[3] = {wrapi(z - 1, g.nz), z, wrapi(z + 1, g.nz)};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * (ys[j] + g.ny * zs[l]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * ys[j];
+        }
+    }
+    // node index of r + k*c for k = +-1
+    __device__ __forceinline__ int at(int dx, int dy, int dz) const { return xs[1 + dx] + ro[1 + dy][1 + dz]; }
+};
+
+// pull gather of the Q populations arriving at node n (= r) at this time step
+template <int D, class S, class C, bool MASK>
+__device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, const uint8_t *__restrict__ mask,
+                                       const Nbr<D> &nb, int n, C (&h)[Lat<D>::Q]) {
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        if constexpr (i == 0) {
+            h[0] = C(A[n]);
+        } else {
+            const int s = nb.at(-cx, -cy, -cz);
+            if constexpr (MASK) {
+                h[i] = mask[s] ? C(A[(long long)opp<D>(i) * qs + n]) : C(A[(long long)i * qs + s]);
+            } else {
+                h[i] = C(A[(long long)i * qs + s]);
+            }
+        }
+    });
+}
+
+// sum h and j = sum c h in a fixed order (pass 1 and pass 2 must agree bit for bit)
+template <int D, class C>
+__device__ __forceinline__ void moments_of(const C (&h)[Lat<D>::Q], C &sum, C (&j)[3]) {
+    sum = C(0);
+    j[0] = j[1] = j[2] = C(0);
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        sum += h[i];
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ca = Lat<D>::c(i, a);
+            if constexpr (ca == 1) j[a] += h[i];
+            if constexpr (ca == -1) j[a] -= h[i];
+        });
+    });
+}
+
+// Product-form equilibrium and extended equilibrium in deviation form, then LBGK.
+// Per axis the triplet Psi_c(xi, zeta) = W_c + d_c with W = (1/6, 2/3, 1/6) for
+// c = (-1, 0, 1); the products are differenced by telescoping so no O(1) terms cancel.
+template <int D, class C>
+__device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const C (&u)[3], const C (&S)[3],
+                                        const C (&Phi)[3], C omega) {
+    constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
+    C dv[3][3], Av[3][3], Dv[3][3], Bv[3][3];
+    const C rinv = C(1) / rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const C ua = u[a], u2 = ua * ua;
+        dv[a][0] = C(0.5) * (u2 - ua);
+        dv[a][1] = -u2;
+        dv[a][2] = C(0.5) * (u2 + ua);
+        const C s = S[a] * rinv;                       // xi* - u
+        const C de = s * (C(2) * ua + s) + Phi[a] * rinv; // zeta* - zeta_eq
+        Dv[a][0] = C(0.5) * (de - s);
+        Dv[a][1] = -de;
+        Dv[a][2] = C(0.5) * (de + s);
+        Av[a][0] = W0 + dv[a][0]; Av[a][1] = W1 + dv[a][1]; Av[a][2] = W0 + dv[a][2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Bv[a][k] = Av[a][k] + Dv[a][k];
+    }
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int kx = Lat<D>::c(i, 0) + 1, ky = Lat<D>::c(i, 1) + 1, kz = Lat<D>::c(i, 2) + 1;
+        constexpr C Wx = kx == 1 ? W1 : W0, Wy = ky == 1 ? W1 : W0;
+        constexpr C wi = C(weight<D>(i));
+        C eqd, fsd;
+        if constexpr (D == 2) {
+            eqd = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
+            fsd = Dv[0][kx] * Bv[1][ky] + Av[0][kx] * Dv[1][ky];
+        } else {
+            eqd = dv[0][kx] * Av[1][ky] * Av[2][kz] + Wx * dv[1][ky] * Av[2][kz] + Wx * Wy * dv[2][kz];
+            fsd = Dv[0][kx] * Bv[1][ky] * Bv[2][kz] + Av[0][kx] * Dv[1][ky] * Bv[2][kz] +
+                  Av[0][kx] * Av[1][ky] * Dv[2][kz];
+        }
+        const C heq = drho * wi + rho * eqd;
+        h[i] = h[i] + omega * (heq - h[i]) + rho * fsd;
+    });
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block of 256 threads: sums 5 values in a fixed order, thread 0 writes them
+__device__ __forceinline__ void block_sum5(double (&v)[kPartialSlots], double *__restrict__ dst) {
+    __shared__ double red[4][kPartialSlots];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kPartialSlots; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kPartialSlots; ++k) red[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < kPartialSlots) {
+        const int k = threadIdx.x;
+        dst[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    }
+}
+
+// ------------------------------------------------------------------ pass 1
+template <int D, class S, class C, bool MASK>
+__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g, const uint8_t *__restrict__ mask,
+                                                 Params<C> p, C *__restrict__ rho_out, C *__restrict__ gf,
+                                                 double *__restrict__ partials) {
+    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+    const int x = blockIdx.x * TX + tx, y = blockIdx.y * TY + ty, z = blockIdx.z;
+    double v[kPartialSlots] = {0, 0, 0, 0, 0};
+    if (x < g.nx && y < g.ny) {
+        const int n = x + g.nx * (y + g.ny * z);
+        C rho, ga[3] = {C(0), C(0), C(0)};
+        if (MASK && mask[n]) {
+            rho = p.rho_w;
+        } else {
+            Nbr<D> nb(g, x, y, z);
+            C h[Lat<D>::Q];
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h);
+            C sum, j[3];
+            moments_of<D, C>(h, sum, j);
+            rho = p.rho_ref + sum;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const C ua = j[a] / rho;
+                ga[a] = rho * ua * ua * ua;
+            }
+            v[0] = double(rho);
+            v[1] = double(j[0]);
+            v[2] = double(j[1]);
+            v[3] = D == 3 ? double(j[2]) : 0.0;
+            v[4] = p.eos.in_domain(rho) ? 0.0 : 1.0;
+        }
+        rho_out[n] = rho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) gf[(long long)a * g.N + n] = ga[a];
+    }
+    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum5(v, partials + (long long)blk * kPartialSlots);
+}
+
+// ------------------------------------------------------------------ pass 2
+template <int D> struct Tile {
+    static constexpr int ZB = D == 3 ? 2 : 1;                  // z-planes per workgroup
+    static constexpr int LX = TX + 2 * HALO, LY = TY + 2 * HALO;
+    static constexpr int LZ = D == 3 ? ZB + 2 * HALO : 1;
+    static constexpr int LS = LX * LY * LZ;
+};
+
+template <int D, class S, class C, bool MASK, bool OUT>
+__global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__restrict__ B, Geom g,
+                                                 const uint8_t *__restrict__ mask, Params<C> p,
+                                                 const C *__restrict__ rho_f, const C *__restrict__ gf,
+                                                 double *__restrict__ out_rho, double *__restrict__ out_U) {
+    using T = Tile<D>;
+    __shared__ C s_rho[T::LS];
+    __shared__ C s_psi[T::LS];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
+    for (int e = threadIdx.x; e < T::LS; e += 256) {
+        const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
+        const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
+        const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
+        const C r = rho_f[gx + g.nx * (gy + g.ny * gz)];
+        s_rho[e] = r;
+        s_psi[e] = signed_psi(p.eos, r);
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+#pragma unroll 1
+    for (int zz = 0; zz < T::ZB; ++zz) {
+        const int z = z0 + zz;
+        if (z >= g.nz) break;
+        const int n = x + g.nx * (y + g.ny * z);
+        if (MASK && mask[n]) {
+            if constexpr (OUT) {
+                out_rho[n] = double(p.rho_w);
+                for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = 0.0;
+            }
+            continue;
+        }
+        const int lc = ((D == 3 ? zz + HALO : 0) * T::LY + ty + HALO) * T::LX + tx + HALO;
+        const C rho = s_rho[lc], spc = s_psi[lc];
+        C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
+        static_for<1, Lat<D>::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+            constexpr int off = (cz * T::LY + cy) * T::LX + cx;
+            constexpr C w3 = C(3.0 * weight<D>(i));
+            const C p1 = fabs(s_psi[lc + off]), p2 = fabs(s_psi[lc + 2 * off]);
+            const C r1 = s_rho[lc + off], r2 = s_rho[lc + 2 * off];
+            const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
+            const C tc = w3 * (C(2) * r1 - r2);
+            static_for<0, D>([&](auto A_) {
+                constexpr int a = decltype(A_)::value;
+                constexpr int ca = Lat<D>::c(i, a);
+                if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
+                if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
+            });
+        });
+        C Sf[3] = {C(0), C(0), C(0)};
+#pragma unroll
+        for (int a = 0; a < D; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);   // S = -F
+
+        Nbr<D> nb(g, x, y, z);
+        C h[Lat<D>::Q];
+        gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h);
+        C drho, j[3];
+        moments_of<D, C>(h, drho, j);
+        C u[3] = {C(0), C(0), C(0)};
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = j[a] / rho;
+        const C omega = omega_of(p, rho);
+        C Phi[3] = {C(0), C(0), C(0)};
+        {
+            const C cf = (C(1) - C(0.5) * omega) * C(0.5);
+            Phi[0] = cf * (gf[nb.at(1, 0, 0)] - gf[nb.at(-1, 0, 0)]);
+            Phi[1] = cf * (gf[(long long)g.N + nb.at(0, 1, 0)] - gf[(long long)g.N + nb.at(0, -1, 0)]);
+            if constexpr (D == 3)
+                Phi[2] = cf * (gf[2LL * g.N + nb.at(0, 0, 1)] - gf[2LL * g.N + nb.at(0, 0, -1)]);
+        }
+        if constexpr (OUT) {
+            out_rho[n] = double(rho);
+#pragma unroll
+            for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = double(u[a] + Sf[a] / (C(2) * rho));
+        } else {
+            collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
+            static_for<0, Lat<D>::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                B[(long long)i * g.qs + n] = S(h[i]);
+            });
+        }
+    }
+}
+
+// ------------------------------------------------------------------ init
+template <int D, class S, class C, bool MASK>
+__global__ __launch_bounds__(256) void k_init(S *__restrict__ A, Geom g, const uint8_t *__restrict__ mask, Params<C> p,
+                                              const double *__restrict__ rho0, const double *__restrict__ u0) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= g.N) return;
+    if (MASK && mask[n]) return;
+    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+    const C rho = C(rho0[n]);
+    C u[3] = {C(0), C(0), C(0)};
+    if (u0)
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = C(u0[(long long)a * g.N + n]);
+    C h[Lat<D>::Q];
+#pragma unroll
+    for (int i = 0; i < Lat<D>::Q; ++i) h[i] = C(0);
+    // with omega = 1, S = 0, Phi = 0 the update returns exactly the equilibrium deviation
+    const C zero3[3] = {C(0), C(0), C(0)};
+    collide<D, C>(h, rho, rho - p.rho_ref, u, zero3, zero3, C(1));
+    Nbr<D> nb(g, x, y, z);
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        if constexpr (i == 0) {
+            A[n] = S(h[0]);
+        } else {
+            // pulled at n from n - c_i, or from opp(i) at n when n - c_i is solid
+            const int s = nb.at(-cx, -cy, -cz);
+            if (MASK && mask[s])
+                A[(long long)opp<D>(i) * g.qs + n] = S(h[i]);
+            else
+                A[(long long)i * g.qs + s] = S(h[i]);
+        }
+    });
+}
+
+template <class S> __global__ __launch_bounds__(256) void k_fill_zero(S *__restrict__ A, long long count) {
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < count; k += (long long)gridDim.x * 256)
+        A[k] = S(0);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partials, int nblocks,
+                                                double *__restrict__ totals) {
+    __shared__ double red[256][kPartialSlots];
+    double acc[kPartialSlots] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < kPartialSlots; ++k) acc[k] += partials[(long long)b * kPartialSlots + k];
+#pragma unroll
+    for (int k = 0; k < kPartialSlots; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < kPartialSlots; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < kPartialSlots) totals[threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ------------------------------------------------------------------ launchers
+dim3 moment_grid(int D, const Geom &g) {
+    return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? g.nz : 1);
+}
+
+template <int D, class S, class C, bool MASK> struct Launch {
+    static void fill_zero(hipStream_t s, void *A, long long count) {
+        long long blocks = (count + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_fill_zero<S>, dim3((unsigned)blocks), dim3(256), 0, s, (S *)A, count);
+    }
+    static void init(hipStream_t s, void *A, const Geom &g, const uint8_t *mask, const void *prm, const double *rho0,
+                     const double *u0) {
+        hipLaunchKernelGGL((k_init<D, S, C, MASK>), dim3((g.N + 255) / 256), dim3(256), 0, s, (S *)A, g, mask,
+                           *(const Params<C> *)prm, rho0, u0);
+    }
+    static void moments(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm, void *rho,
+                        void *gfl, double *partials) {
+        hipLaunchKernelGGL((k_moments<D, S, C, MASK>), moment_grid(D, g), dim3(256), 0, s, (const S *)A, g, mask,
+                           *(const Params<C> *)prm, (C *)rho, (C *)gfl, partials);
+    }
+    static dim3 collide_grid(const Geom &g) {
+        return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? (g.nz + Tile<D>::ZB - 1) / Tile<D>::ZB : 1);
+    }
+    static void collide(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm,
+                        const void *rho, const void *gfl) {
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, false>), collide_grid(g), dim3(256), 0, s, (const S *)A, (S *)B, g,
+                           mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, nullptr, nullptr);
+    }
+    static void output(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm,
+                       const void *rho, const void *gfl, double *orho, double *oU) {
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, true>), collide_grid(g), dim3(256), 0, s, (const S *)A,
+                           (S *)nullptr, g, mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, orho, oU);
+    }
+    static KernelSet set() {
+        KernelSet k;
+        k.fill_zero = fill_zero;
+        k.init = init;
+        k.moments = moments;
+        k.collide = collide;
+        k.output = output;
+        k.moment_blocks = 0;
+        return k;
+    }
+};
+
+}  // namespace
+
+int moment_block_count(int D, const Geom &g) {
+    dim3 gr = moment_grid(D, g);
+    return (int)(gr.x * gr.y * gr.z);
+}
+
+KernelSet kernel_set(int D, bool fp64, bool masked) {
+    if (D == 2) {
+        if (fp64) return masked ? Launch<2, double, double, true>::set() : Launch<2, double, double, false>::set();
+        return masked ? Launch<2, float, float, true>::set() : Launch<2, float, float, false>::set();
+    }
+    if (fp64) return masked ? Launch<3, double, double, true>::set() : Launch<3, double, double, false>::set();
+    return masked ? Launch<3, float, float, true>::set() : Launch<3, float, float, false>::set();
+}
+
+void launch_reduce(hipStream_t s, const double *partials, int nblocks, double *totals) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nblocks, totals);
+}
+
+}  // namespace lbm

@@ -1,0 +1,285 @@
+"""Thin ctypes binding of liblbm2p.so (C ABI in include/lbm2p.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP library.
+The functions keep the C names; host arrays are NumPy float64 (uint8 for masks).
+Importing this module never falls back to anything: a missing or unloadable
+library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm2p.so")
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_DOMAIN, LBM_E_DIVERGED, LBM_E_STATE = 0, -1, -2, -3, -4, -5, -6
+LBM_D2Q9, LBM_D3Q27 = 0, 1
+LBM_EOS_VDW, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_CS, LBM_EOS_IDEAL = 0, 1, 2, 3, 4
+LBM_FP64, LBM_FP32_DEV = 0, 1
+
+EXPORTED = [
+    "lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments", "lbm_destroy", "lbm_last_error",
+    "lbm_set_stream", "lbm_population_bytes", "lbm_get_populations", "lbm_set_populations",
+    "lbm_step_timed", "lbm_coexistence", "lbm_kappa_for_width", "lbm_batch_create",
+    "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
+    "lbm_batch_last_error",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class lbm_params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("eos", C.c_int), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
+        ("acentric", C.c_double), ("T_reduced", C.c_double), ("kappa", C.c_double),
+        ("tau_liquid", C.c_double), ("tau_vapour", C.c_double),
+        ("rho_liquid", C.c_double), ("rho_vapour", C.c_double), ("rho_wall", C.c_double),
+        ("mask", C.c_void_p), ("precision", C.c_int), ("rho_ref", C.c_double), ("check_every", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2112_01975_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, d, i64 = C.c_void_p, C.c_double, C.c_int64
+        P = C.POINTER(lbm_params)
+        L.lbm_create.argtypes = [P, C.POINTER(vp)]
+        L.lbm_init_fields.argtypes = [vp, vp, vp]
+        L.lbm_step.argtypes = [vp, i64]
+        L.lbm_moments.argtypes = [vp, vp, vp, vp]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = C.c_char_p
+        L.lbm_set_stream.argtypes = [vp, vp]
+        L.lbm_population_bytes.argtypes = [vp]
+        L.lbm_population_bytes.restype = i64
+        L.lbm_get_populations.argtypes = [vp, vp]
+        L.lbm_set_populations.argtypes = [vp, vp]
+        L.lbm_step_timed.argtypes = [vp, i64, vp, vp]
+        L.lbm_coexistence.argtypes = [P, vp]
+        L.lbm_kappa_for_width.argtypes = [P, d, C.POINTER(d)]
+        L.lbm_batch_create.argtypes = [P, C.c_int, C.POINTER(vp)]
+        L.lbm_batch_init_fields.argtypes = [vp, C.c_int, vp, vp]
+        L.lbm_batch_step.argtypes = [vp, i64]
+        L.lbm_batch_moments.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
+        L.lbm_batch_last_error.argtypes = [vp]
+        L.lbm_batch_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc: int, ctx=None, batch=False):
+    if rc != LBM_OK:
+        if batch:
+            msg = lib().lbm_batch_last_error(ctx)
+        else:
+            msg = lib().lbm_last_error(ctx)
+        raise LbmError(rc, (msg or b"").decode())
+    return rc
+
+
+@dataclass
+class Params:
+    """Problem statement of one simulation; see lbm_params in include/lbm2p.h."""
+    lattice: int
+    nx: int
+    ny: int
+    nz: int = 1
+    eos: int = LBM_EOS_VDW
+    a: float = 9.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    acentric: float = 0.0
+    T_reduced: float = 0.9
+    kappa: float = 0.02
+    tau_liquid: float = 0.8
+    tau_vapour: float = 0.0
+    rho_liquid: float = 0.0
+    rho_vapour: float = 0.0
+    rho_wall: float = 0.0
+    mask: np.ndarray | None = None
+    precision: int = LBM_FP64
+    rho_ref: float = 0.0
+    check_every: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def D(self) -> int:
+        return 3 if self.lattice == LBM_D3Q27 else 2
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def to_c(self) -> lbm_params:
+        m = None
+        if self.mask is not None:
+            m = np.ascontiguousarray(self.mask, dtype=np.uint8)
+            self._keep = [m]
+        return lbm_params(self.lattice, self.nx, self.ny, self.nz, self.eos, self.a, self.b, self.R,
+                          self.acentric, self.T_reduced, self.kappa, self.tau_liquid, self.tau_vapour,
+                          self.rho_liquid, self.rho_vapour, self.rho_wall, _ptr(m), self.precision,
+                          self.rho_ref, self.check_every)
+
+
+# ----------------------------------------------------------------- C-named wrappers
+def lbm_create(p: Params) -> C.c_void_p:
+    cp = p.to_c()
+    h = C.c_void_p()
+    _check(lib().lbm_create(C.byref(cp), C.byref(h)), None)
+    return h
+
+
+def lbm_init_fields(ctx, rho: np.ndarray, u: np.ndarray | None = None):
+    rho, u = _f64(rho), _f64(u)
+    _check(lib().lbm_init_fields(ctx, _ptr(rho), _ptr(u)), ctx)
+
+
+def lbm_step(ctx, n: int):
+    _check(lib().lbm_step(ctx, int(n)), ctx)
+
+
+def lbm_moments(ctx, N: int, D: int, want_fields: bool = True):
+    rho = np.empty(N) if want_fields else None
+    U = np.empty((D, N)) if want_fields else None
+    tot = np.empty(4)
+    _check(lib().lbm_moments(ctx, _ptr(rho), _ptr(U), _ptr(tot)), ctx)
+    return rho, U, tot
+
+
+def lbm_destroy(ctx):
+    if ctx:
+        lib().lbm_destroy(ctx)
+
+
+def lbm_last_error(ctx=None) -> str:
+    return (lib().lbm_last_error(ctx) or b"").decode()
+
+
+def lbm_set_stream(ctx, stream_handle: int | None):
+    _check(lib().lbm_set_stream(ctx, stream_handle), ctx)
+
+
+def lbm_population_bytes(ctx) -> int:
+    return int(lib().lbm_population_bytes(ctx))
+
+
+def lbm_get_populations(ctx) -> np.ndarray:
+    buf = np.empty(lbm_population_bytes(ctx), dtype=np.uint8)
+    _check(lib().lbm_get_populations(ctx, _ptr(buf)), ctx)
+    return buf
+
+
+def lbm_set_populations(ctx, buf: np.ndarray):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib().lbm_set_populations(ctx, _ptr(buf)), ctx)
+
+
+def lbm_step_timed(ctx, n: int):
+    ms = np.zeros(3)
+    nl = np.zeros(2, dtype=np.int64)
+    _check(lib().lbm_step_timed(ctx, int(n), _ptr(ms), _ptr(nl)), ctx)
+    return ms, nl
+
+
+def lbm_coexistence(p: Params):
+    cp = p.to_c()
+    out = np.zeros(4)
+    _check(lib().lbm_coexistence(C.byref(cp), _ptr(out)), None)
+    return tuple(out)          # rho_v, rho_l, P_sat, T
+
+
+def lbm_kappa_for_width(p: Params, width: float) -> float:
+    cp = p.to_c()
+    k = C.c_double()
+    _check(lib().lbm_kappa_for_width(C.byref(cp), float(width), C.byref(k)), None)
+    return k.value
+
+
+def lbm_batch_create(cases: list[Params]):
+    arr = (lbm_params * len(cases))(*[c.to_c() for c in cases])
+    h = C.c_void_p()
+    _check(lib().lbm_batch_create(arr, len(cases), C.byref(h)), None, batch=True)
+    return h
+
+
+def lbm_batch_init_fields(b, icase: int, rho, u=None):
+    rho, u = _f64(rho), _f64(u)
+    _check(lib().lbm_batch_init_fields(b, icase, _ptr(rho), _ptr(u)), b, batch=True)
+
+
+def lbm_batch_step(b, n: int):
+    _check(lib().lbm_batch_step(b, int(n)), b, batch=True)
+
+
+def lbm_batch_moments(b, icase: int, N: int, D: int):
+    rho, U, tot = np.empty(N), np.empty((D, N)), np.empty(4)
+    _check(lib().lbm_batch_moments(b, icase, _ptr(rho), _ptr(U), _ptr(tot)), b, batch=True)
+    return rho, U, tot
+
+
+def lbm_batch_destroy(b):
+    if b:
+        lib().lbm_batch_destroy(b)
+
+
+class Simulation:
+    """Owns one context; convenience over the C-named functions."""
+
+    def __init__(self, p: Params):
+        self.p = p
+        self.ctx = lbm_create(p)
+
+    def init(self, rho, u=None):
+        lbm_init_fields(self.ctx, rho, u)
+        return self
+
+    def step(self, n: int):
+        lbm_step(self.ctx, n)
+        return self
+
+    def moments(self, want_fields: bool = True):
+        return lbm_moments(self.ctx, self.p.N, self.p.D, want_fields)
+
+    def close(self):
+        if self.ctx:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: FP64 storage -> max relative density error <= 1e-10 and velocity error
+<= 1e-10 (absolute, lattice units) after the stated steps; FP32 deviation
+storage -> the per-case tolerance written in the test, derived from FP32
+rounding (unit roundoff 6e-8) accumulated over the run.
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+from oracle import thermo as T
+from tests.gpu_cases import Case, drop_case_inputs, max_rel, run_gpu, run_oracle, slab_case_inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_RHO_TOL = 1e-10
+FP64_U_TOL = 1e-10
+
+
+def _cmp64(case, rho0, u0, steps):
+    r_o, U_o, t_o = run_oracle(case, rho0, u0, steps)
+    r_g, U_g, t_g = run_gpu(case, rho0, u0, steps)
+    assert np.all(np.isfinite(r_g))
+    err_r = max_rel(r_g, r_o)
+    err_u = float(np.abs(U_g - U_o).max())
+    assert err_r <= FP64_RHO_TOL, f"max rel rho error {err_r:.3e}"
+    assert err_u <= FP64_U_TOL, f"max U error {err_u:.3e}"
+    assert abs(t_g[0] - t_o[0]) <= 1e-12 * abs(t_o[0])
+    return err_r, err_u, t_g
+
+
+def test_flat_interface_d2q9_64x64_fp64_1000_steps():
+    # vdW a = 9/49, b = 2/21 at T/Tc = 0.9, slab in the middle half, tanh width 4, noise 1e-4
+    case = Case(2, 64, 64)
+    rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 1001)
+    _, _, tot = _cmp64(case, rho0, u0, 1000)
+    assert abs(tot[0] - rho0.sum()) <= 1e-13 * rho0.sum()     # exact mass conservation
+
+
+def test_static_drop_d2q9_ragged_fp64():
+    # 100 x 70: two x-tiles with a ragged tail, y not a multiple of the tile height
+    case = Case(2, 100, 70, a=0.0225, T_reduced=0.8)
+    rho0, u0 = drop_case_inputs(case, 20.0, 4.0, 1e-4, 1002)
+    _cmp64(case, rho0, u0, 400)
+
+
+@pytest.mark.parametrize("eos,a,om,tr", [(T.VDW, 0.02, 0.0, 0.7), (T.PR, 0.005, 0.344, 0.6),
+                                        (T.RKS, 0.01, 0.344, 0.7), (T.CS, 0.005, 0.0, 0.7)])
+def test_every_eos_d2q9_fp64(eos, a, om, tr):
+    case = Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr)
+    rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 7)
+    _cmp64(case, rho0, u0, 300)
+
+
+def test_ideal_gas_shear_wave_fp64():
+    case = Case(2, 40, 8, eos=T.IDEAL, kappa=0.0, tau=0.7)
+    x = np.tile(np.arange(40), 8).astype(float)
+    u0 = np.zeros((2, case.N)); u0[1] = 1e-3 * np.sin(2 * np.pi * x / 40)
+    _cmp64(case, np.ones(case.N), u0, 200)
+
+
+def test_drop_d3q27_periodic_fp64():
+    # PR at T/Tc = 0.6 (density ratio 853); 70 x 36 x 20: x ragged over two tiles
+    case = Case(3, 70, 36, 20, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rho0, u0 = drop_case_inputs(case, 8.0, 5.0, 1e-5, 1003, centre=(35.0, 18.0, 10.0))
+    _cmp64(case, rho0, u0, 100)
+
+
+def test_textured_wall_d3q27_variable_viscosity_fp64():
+    # pillar mask with floor, two viscosities, moving drop (drop-impact shape, reduced size)
+    nx, ny, nz = 32, 32, 40
+    mask = L.pillar_mask(nx, ny, nz, 4, 4, 6)
+    fl = T.Fluid(T.PR, 0.0037104, 2 / 21, 0.5, 1.0, 0.344)
+    rv, rl, _ = T.coexistence(fl)
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.0037104, acentric=0.344, T_reduced=0.5, tau=0.55,
+                tau_vapour=0.5 + 15 * 0.05, rho_wall=rv, mask=mask)
+    rho0 = L.drop(nx, ny, nz, 8.0, rl, rv, 5.0, centre=(16.0, 16.0, 22.0), noise=1e-5, seed=1005)
+    u0 = L.impact_drop_velocity(rho0, rl, rv, 3, -0.05, 2)
+    _cmp64(case, rho0, u0, 60)
+
+
+def test_random_mask_d2q9_fp64():
+    nx, ny = 37, 29
+    mask = L.random_mask(nx, ny, 1, 0.1, 21)
+    fl = T.Fluid(T.VDW, 0.02, 2 / 21, 0.8)
+    rv, rl, _ = T.coexistence(fl)
+    case = Case(2, nx, ny, a=0.02, T_reduced=0.8, rho_wall=0.5 * (rv + rl), mask=mask,
+                tau_vapour=0.9)
+    rho0, u0 = L.random_state(nx * ny, 2, rv, rl, 0.02, 31)
+    _cmp64(case, rho0, u0, 150)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 1), (3, 5, 1), (5, 1, 1)])
+def test_degenerate_tiny_periodic_d2q9(dims):
+    # grids smaller than the two-ring stencil: neighbours wrap onto the node itself
+    nx, ny, _ = dims
+    case = Case(2, nx, ny, a=0.02, T_reduced=0.8)
+    fl = case.fluid()
+    rv, rl, _ = T.coexistence(fl)
+    rho0, u0 = L.random_state(nx * ny, 2, rv, 0.5 * (rv + rl), 0.02, 41)
+    _cmp64(case, rho0, u0, 50)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 2, 4), (65, 1, 3)])
+def test_degenerate_tiny_periodic_d3q27(dims):
+    nx, ny, nz = dims
+    case = Case(3, nx, ny, nz, a=0.02, T_reduced=0.8)
+    rv, rl, _ = T.coexistence(case.fluid())
+    rho0, u0 = L.random_state(nx * ny * nz, 3, rv, 0.5 * (rv + rl), 0.02, 43)
+    _cmp64(case, rho0, u0, 30)
+
+
+def test_init_then_moments_returns_inputs():
+    case = Case(3, 20, 12, 9, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rho0, u0 = L.random_state(case.N, 3, 0.1, 5.0, 0.05, 3)
+    r_g, U_g, _ = run_gpu(case, rho0, u0, 0)
+    r_o, U_o, _ = run_oracle(case, rho0, u0, 0)
+    assert max_rel(r_g, rho0) < 1e-14
+    assert np.abs(U_g - U_o).max() < 1e-12
+
+
+# ---------------------------------------------------------------- FP32 deviation storage
+def test_fp32_dev_flat_interface_error_stated():
+    # FP32 storage of f - w rho_ref with rho_ref = rho_v; 1000 steps of the 64x64 flat interface
+    case = Case(2, 64, 64)
+    rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 1001)
+    rv, rl = case.coexistence()
+    r_o, U_o, t_o = run_oracle(case, rho0, u0, 1000)
+    r_g, U_g, t_g = run_gpu(case, rho0, u0, 1000, precision=1, rho_ref=rv)
+    err = max_rel(r_g, r_o)
+    assert err < 2e-5, f"FP32 max rel rho error {err:.3e}"
+    assert abs(t_g[0] - t_o[0]) / t_o[0] < 1e-6                       # mass drift
+
+
+def test_fp32_dev_drop_d3q27_error_stated():
+    case = Case(3, 48, 48, 48, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rho0, u0 = drop_case_inputs(case, 12.0, 5.0, 1e-5, 1003)
+    rv, rl = case.coexistence()
+    r_o, _, t_o = run_oracle(case, rho0, u0, 100)
+    r_g, _, t_g = run_gpu(case, rho0, u0, 100, precision=1, rho_ref=rv)
+    err = max_rel(r_g, r_o)
+    assert err < 1e-4, f"FP32 max rel rho error {err:.3e}"
+    assert abs(t_g[0] - t_o[0]) / t_o[0] < 1e-6
+
+
+# ---------------------------------------------------------------- runtime behaviour
+def test_checkpoint_resume_bitwise():
+    import paper_2112_01975_amd as P
+    case = Case(3, 24, 20, 16, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rho0, u0 = drop_case_inputs(case, 6.0)
+    for prec in (0, 1):
+        with P.Simulation(case.params(prec, 0.01)) as s:
+            s.init(rho0, u0).step(10)
+            snap = P.lbm_get_populations(s.ctx)
+            s.step(15)
+            r1, U1, _ = s.moments()
+            P.lbm_set_populations(s.ctx, snap)
+            s.step(15)
+            r2, U2, _ = s.moments()
+        assert np.array_equal(r1, r2) and np.array_equal(U1, U2)
+
+
+def test_repeat_run_is_bitwise_deterministic():
+    case = Case(3, 40, 24, 12, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rho0, u0 = drop_case_inputs(case, 7.0)
+    a = run_gpu(case, rho0, u0, 20, precision=1, rho_ref=0.0102)
+    b = run_gpu(case, rho0, u0, 20, precision=1, rho_ref=0.0102)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_watchdog_reports_divergence_and_domain():
+    import paper_2112_01975_amd as P
+    case = Case(2, 16, 8, a=0.02, T_reduced=0.8)
+    rv, rl = case.coexistence()
+    with P.Simulation(case.params(0, 0.0, check_every=1)) as s:
+        s.init(np.full(case.N, rv))
+        snap = P.lbm_get_populations(s.ctx).view(np.float64).copy()
+        snap[5] = np.nan
+        with pytest.raises(P.LbmError) as ei:
+            P.lbm_set_populations(s.ctx, snap.view(np.uint8))
+        assert ei.value.code == P.LBM_E_DIVERGED
+        with pytest.raises(P.LbmError) as ei:
+            s.step(1)                                   # sticky until re-initialised
+        assert ei.value.code == P.LBM_E_DIVERGED
+        s.init(np.full(case.N, rv)).step(3)             # recovers
+    with P.Simulation(case.params()) as s:
+        with pytest.raises(P.LbmError) as ei:
+            s.init(np.full(case.N, 1.0 / case.b + 1.0))   # b rho >= 1
+        assert ei.value.code == P.LBM_E_DOMAIN
