@@ -161,8 +161,37 @@ def log_spaced_int(lo: int, hi: int, count: int) -> list[int]:
     return [int(round(lo * (hi / lo) ** (k / (count - 1)))) for k in range(count)]
 
 
+def equimolar_offset(profile: np.ndarray, rho_liquid: float, rho_vapour: float) -> float:
+    """Position (in nodes from index 0) of the equimolar surface of a monotone
+    vapour->liquid profile: the excess mass left of it equals the deficit right of it."""
+    excess = float(np.sum(profile - rho_vapour))
+    return len(profile) - excess / (rho_liquid - rho_vapour)
+
+
+def radial_from_profile(nx: int, ny: int, nz: int, radius: float, profile: np.ndarray,
+                        centre=None, noise: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Drop whose radial density follows a given 1D vapour->liquid profile.
+
+    `profile` samples the density at unit spacing across one flat interface,
+    vapour at index 0 and liquid at the end; its equimolar surface is placed at
+    distance `radius` from the centre, and the ends are held constant beyond the
+    sampled range.
+    """
+    profile = np.asarray(profile, dtype=np.float64)
+    rv, rl = float(profile[0]), float(profile[-1])
+    xe = equimolar_offset(profile, rl, rv)
+    d_grid = np.arange(len(profile)) - xe + 0.5
+    x, y, z = _grid(nx, ny, nz)
+    if centre is None:
+        centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
+    cx, cy, cz = centre
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + ((z - cz) ** 2 if nz > 1 else 0.0))
+    rho = np.interp(radius - r, d_grid, profile, left=rv, right=rl)
+    return add_noise(rho, seed, noise)
+
+
 __all__ = [
     "splitmix64", "uniform_pm", "tanh_profile", "add_noise", "flat_slab", "drop", "zero_velocity",
     "liquid_fraction", "pillar_mask", "random_mask", "random_state", "SweepCase", "temperature_sweep",
-    "impact_drop_velocity", "log_spaced_int",
+    "impact_drop_velocity", "log_spaced_int", "equimolar_offset", "radial_from_profile",
 ]

@@ -63,9 +63,12 @@ class BruteForce:
     def _idx(self, c):
         return tuple(ci + 1 for ci in c)
 
-    def init(self, rho, u=None):
+    def init(self, rho, U=None):
+        """f = f_eq(rho, u) with u = U - S/(2 rho): U is the flow velocity (Appendix D)."""
         rho = rho.reshape(self.shape)
-        u = np.zeros((self.D,) + self.shape) if u is None else u.reshape((self.D,) + self.shape)
+        U = np.zeros((self.D,) + self.shape) if U is None else U.reshape((self.D,) + self.shape)
+        S = self._source(np.where(self.solid, self.rho_wall, rho))
+        u = U - S / (2.0 * rho)
         self.f = _cube(rho, list(u), [1.0 / 3.0 + ua * ua for ua in u])
         self.f[(slice(None),) * self.D + (self.solid,)] = 0.0
         return self
@@ -77,16 +80,9 @@ class BruteForce:
         s = np.clip((rho - self.rv) / (self.rl - self.rv), 0.0, 1.0)
         return 1.0 / (3.0 * (nv + (nl - nv) * s) + 0.5)
 
-    def fields(self):
+    def _source(self, rho):
+        """S = -F for eq Kforce_final on a density field (solid nodes already hold rho_w)."""
         D = self.D
-        vaxes = tuple(range(D))
-        rho = self.f.sum(axis=vaxes)
-        j = []
-        for a in range(D):
-            ca = np.array([-1.0, 0.0, 1.0]).reshape([3 if b == a else 1 for b in range(D)] + [1] * D)
-            j.append((ca * self.f).sum(axis=vaxes))
-        rho = np.where(self.solid, self.rho_wall, rho)
-        u = np.stack([np.where(self.solid, 0.0, ja / rho) for ja in j])
         P = self.fluid.pressure(rho)
         P0 = rho / 3.0
         psi = np.sqrt(np.abs(P - P0))
@@ -102,7 +98,19 @@ class BruteForce:
                     Fpsi[a] += c[a] * tp
                     Fcap[a] += c[a] * tc
         F = 2.0 * sgn * psi * Fpsi + self.kappa * rho * Fcap
-        S = np.where(self.solid, 0.0, -F)
+        return np.where(self.solid, 0.0, -F)
+
+    def fields(self):
+        D = self.D
+        vaxes = tuple(range(D))
+        rho = self.f.sum(axis=vaxes)
+        j = []
+        for a in range(D):
+            ca = np.array([-1.0, 0.0, 1.0]).reshape([3 if b == a else 1 for b in range(D)] + [1] * D)
+            j.append((ca * self.f).sum(axis=vaxes))
+        rho = np.where(self.solid, self.rho_wall, rho)
+        u = np.stack([np.where(self.solid, 0.0, ja / rho) for ja in j])
+        S = self._source(rho)
         return rho, u, S
 
     def step(self, n=1):

@@ -45,7 +45,8 @@ typedef struct {
     double kappa;
     double tau_liquid, tau_vapour, rho_liquid, rho_vapour;
     double rho_wall;
-    int variant;            /* test-only switches: 1 literal zeta*, 2 literal force sign, 4 no Phi */
+    int variant;            /* test-only switches: 1 literal zeta*, 2 literal force sign, 4 no Phi,
+                               8 initial velocity taken as the bare u */
 } orc_params;
 
 typedef struct {
@@ -221,17 +222,24 @@ void *orc_create(const orc_params *p, const unsigned char *mask)
     return x;
 }
 
-/* f = f_eq(rho0, u0) at fluid nodes (u0 may be NULL = at rest) */
-int orc_init(void *h, const double *rho0, const double *u0)
+/* Initial state from the density and the velocity U of the flow. U is the velocity the
+ * hydrodynamic limit transports (Sec. 2.3.5, Appendix D: U = u + F dt/(2 rho)), so the
+ * bare velocity of the equilibrium is u = U - S/(2 rho), with S the source of the given
+ * density field; f = f_eq(rho0, u) at fluid nodes (U0 may be NULL = at rest). */
+static void source_of_density(orc_ctx *x, const double *rho);
+
+int orc_init(void *h, const double *rho0, const double *U0)
 {
     orc_ctx *x = (orc_ctx *)h;
     long N = x->N;
     int D = x->D, Q = x->Q;
+    source_of_density(x, rho0);
     for (long n = 0; n < N; ++n) {
         double feq[27], xi[3] = {0, 0, 0}, zeta[3];
         if (solid(x, n)) { for (int i = 0; i < Q; ++i) x->f[i * N + n] = 0.0; continue; }
         for (int a = 0; a < D; ++a) {
-            xi[a] = u0 ? u0[a * N + n] : 0.0;
+            double Ua = U0 ? U0[a * N + n] : 0.0;
+            xi[a] = (x->p.variant & 8) ? Ua : Ua - x->S[a * N + n] / (2.0 * rho0[n]);
             zeta[a] = 1.0 / 3.0 + xi[a] * xi[a];
         }
         orc_product_form(D, rho0[n], xi, zeta, feq);
@@ -282,6 +290,33 @@ static void fields(orc_ctx *x)
             double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + p->kappa * x->rho[n] * Fc[a];
             double s = (p->variant & 2) ? F : -F;
             x->S[a * N + n] = (solid(x, n) || a >= D) ? 0.0 : s;
+        }
+    }
+}
+
+/* steps 2-4 for a given density field (solid nodes read as rho_w): x->S = -F_K */
+static void source_of_density(orc_ctx *x, const double *rho)
+{
+    long N = x->N;
+    for (long n = 0; n < N; ++n) {
+        double r = solid(x, n) ? x->p.rho_wall : rho[n];
+        x->rho[n] = r;
+        double P = eos_pressure(x, r), P0 = r / 3.0;
+        x->psi[n] = sqrt(fabs(P - P0));
+        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
+    }
+    for (long n = 0; n < N; ++n) {
+        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
+        for (int i = 0; i < x->Q; ++i) {
+            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
+            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
+            double wc = 3.0 * x->w[i] * (2.0 * x->rho[n1] - x->rho[n2]);
+            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
+        }
+        for (int a = 0; a < 3; ++a) {
+            double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * x->rho[n] * Fc[a];
+            double s = (x->p.variant & 2) ? F : -F;
+            x->S[a * N + n] = (solid(x, n) || a >= x->D) ? 0.0 : s;
         }
     }
 }

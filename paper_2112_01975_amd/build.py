@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm2p.so")
 BUILD = os.path.join(ROOT, "_build", "lbm2p")
 
-SOURCES = ["step_kernels.hip", "runtime.hip", "batch.hip", "thermo_host.cpp"]
+SOURCES = ["step_kernels.hip", "fused_kernels.hip", "runtime.hip", "batch.hip", "thermo_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

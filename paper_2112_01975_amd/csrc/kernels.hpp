@@ -33,9 +33,10 @@ constexpr int kPartialSlots = 5;   // sum rho, sum j_x, j_y, j_z, domain-error c
 struct KernelSet {
     // zero the population array (fill kernel, safe under graph capture)
     void (*fill_zero)(hipStream_t, void *A, long long count);
-    // f = f_eq(rho0, u0), written in pull layout with bounce-back links folded in
-    void (*init)(hipStream_t, void *A, const Geom &, const uint8_t *mask, const void *params,
-                 const double *rho0, const double *u0);
+    // f = f_eq(rho0, u) with u = U0 - S/(2 rho0), written in pull layout with bounce-back
+    // links folded in; rho is the compute-precision density scratch field
+    void (*init)(hipStream_t, void *A, const Geom &, const uint8_t *mask, const void *params, void *rho,
+                 const double *rho0, const double *U0);
     // rho and g = rho u^3 of the current state, per-workgroup FP64 partials
     void (*moments)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
                     void *rho, void *g, double *partials);

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
 
 #include "../../include/lbm2p.h"
+#include "fused.hpp"
 #include "kernels.hpp"
 #include "runtime_common.hpp"
 #include "thermo_host.hpp"
@@ -31,6 +33,8 @@ struct lbm_ctx {
     Params<double> pd{};
     Params<float> pf{};
     KernelSet ks{};
+    FusedLaunch fused = nullptr;     // single-pass step when available (D3Q27 FP32)
+    FusedGrid fg{};
     bool initialized = false;
     int sticky = 0;
     double M0 = 0.0;
@@ -91,10 +95,19 @@ int watchdog(lbm_ctx *c) {
 }
 
 int one_step(lbm_ctx *c) {
-    c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
-    c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+    if (c->fused) {
+        c->fused(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->fg);
+    } else {
+        c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+        c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+    }
     void *t = c->A; c->A = c->B; c->B = t;
     return LBM_OK;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
 }
 
 }  // namespace
@@ -120,6 +133,13 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     fill_params(p, &c->pf);
     c->ks = kernel_set(c->D, c->fp64, c->masked);
     c->nblk = moment_block_count(c->D, c->g);
+    // single-pass z-march for D3Q27 (LBM2P_TWO_PASS=1 forces the two-pass step;
+    // LBM2P_FUSED_TY / LBM2P_FUSED_TZ override the tile height and z-chunk length)
+    if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
+        const int ty = env_int("LBM2P_FUSED_TY", 8), tz = env_int("LBM2P_FUSED_TZ", 32);
+        c->fused = fused_launcher(c->fp64, c->masked, ty);
+        if (c->fused) c->fg = fused_grid(c->g, ty, tz > 0 ? tz : 32);
+    }
     const size_t N = (size_t)c->g.N;
     const size_t cbytes = c->fp64 ? 8 : 4;
     hipError_t e;
@@ -162,7 +182,7 @@ int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u) {
     const long long count = (long long)c->Q * c->g.qs;
     c->ks.fill_zero(c->stream, c->A, count);
     c->ks.fill_zero(c->stream, c->B, count);
-    c->ks.init(c->stream, c->A, c->g, c->mask, params_ptr(c), c->io, u ? c->io + N : nullptr);
+    c->ks.init(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->io, u ? c->io + N : nullptr);
     HIP_OR_FAIL(c, hipGetLastError());
     c->sticky = 0;
     c->initialized = true;
@@ -204,9 +224,13 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
     HIP_OR_FAIL(c, hipEventRecord(tot0, c->stream));
     for (int64_t t = 0; t < n; ++t) {
         HIP_OR_FAIL(c, hipEventRecord(ev[0], c->stream));
-        c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+        if (!c->fused)
+            c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
-        c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        if (c->fused)
+            c->fused(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->fg);
+        else
+            c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
         HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;
@@ -226,7 +250,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
     ms[0] = acc[0];
     ms[1] = acc[1];
     ms[2] = tt;
-    launches[0] = n;
+    launches[0] = c->fused ? 0 : n;
     launches[1] = n;
     return LBM_OK;
 }

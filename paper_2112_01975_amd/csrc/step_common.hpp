@@ -1,0 +1,139 @@
+// step_common.hpp -- device code shared by the two-pass and the fused step kernels:
+// pull gather with halfway bounce-back, moments, and the deviation-form collision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    if ((unsigned)v < (unsigned)n) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <class C> __device__ __forceinline__ C omega_of(const Params<C> &p, C rho) {
+    if (!p.var_visc) return p.omega_l;
+    C s = (rho - p.rho_v) / (p.rho_l - p.rho_v);
+    s = s < C(0) ? C(0) : (s > C(1) ? C(1) : s);
+    C nu = p.nu_v + (p.nu_l - p.nu_v) * s;
+    return C(1) / (C(3) * nu + C(0.5));
+}
+
+// wrapped neighbour coordinates of (x, y, z): xs[k] = x + k - 1, ro[j][l] = row offset of (y + j - 1, z + l - 1)
+template <int D> struct Nbr {
+    int xs[3];
+    int ro[3][3];
+    __device__ __forceinline__ Nbr(const Geom &g, int x, int y, int z) {
+        xs[0] = wrapi(x - 1, g.nx); xs[1] = x; xs[2] = wrapi(x + 1, g.nx);
+        int ys[3] = {wrapi(y - 1, g.ny), y, wrapi(y + 1, g.ny)};
+        if constexpr (D == 3) {
+            int zs[3] = {wrapi(z - 1, g.nz), z, wrapi(z + 1, g.nz)};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * (ys[j] + g.ny * zs[l]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * ys[j];
+        }
+    }
+    // node index of r + k*c for k = +-1
+    __device__ __forceinline__ int at(int dx, int dy, int dz) const { return xs[1 + dx] + ro[1 + dy][1 + dz]; }
+};
+
+// pull gather of the Q populations arriving at node n (= r) at this time step
+template <int D, class S, class C, bool MASK>
+__device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, const uint8_t *__restrict__ mask,
+                                       const Nbr<D> &nb, int n, C (&h)[Lat<D>::Q]) {
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        if constexpr (i == 0) {
+            h[0] = C(A[n]);
+        } else {
+            const int s = nb.at(-cx, -cy, -cz);
+            if constexpr (MASK) {
+                h[i] = mask[s] ? C(A[(long long)opp<D>(i) * qs + n]) : C(A[(long long)i * qs + s]);
+            } else {
+                h[i] = C(A[(long long)i * qs + s]);
+            }
+        }
+    });
+}
+
+// sum h and j = sum c h in a fixed order (pass 1 and pass 2 must agree bit for bit)
+template <int D, class C>
+__device__ __forceinline__ void moments_of(const C (&h)[Lat<D>::Q], C &sum, C (&j)[3]) {
+    sum = C(0);
+    j[0] = j[1] = j[2] = C(0);
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        sum += h[i];
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ca = Lat<D>::c(i, a);
+            if constexpr (ca == 1) j[a] += h[i];
+            if constexpr (ca == -1) j[a] -= h[i];
+        });
+    });
+}
+
+// Product-form equilibrium and extended equilibrium in deviation form, then LBGK.
+// drho = sum of the pre-collision deviations (the node's mass minus rho_ref).
+// Per axis the triplet Psi_c(xi, zeta) = W_c + d_c with W = (1/6, 2/3, 1/6) for
+// c = (-1, 0, 1); the products are differenced by telescoping so no O(1) terms cancel.
+template <int D, class C>
+__device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const C (&u)[3], const C (&S)[3],
+                                        const C (&Phi)[3], C omega) {
+    constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
+    C dv[3][3], Av[3][3], Dv[3][3], Bv[3][3];
+    const C rinv = C(1) / rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const C ua = u[a], u2 = ua * ua;
+        dv[a][0] = C(0.5) * (u2 - ua);
+        dv[a][1] = -u2;
+        dv[a][2] = C(0.5) * (u2 + ua);
+        const C s = S[a] * rinv;                       // xi* - u
+        const C de = s * (C(2) * ua + s) + Phi[a] * rinv; // zeta* - zeta_eq
+        Dv[a][0] = C(0.5) * (de - s);
+        Dv[a][1] = -de;
+        Dv[a][2] = C(0.5) * (de + s);
+        Av[a][0] = W0 + dv[a][0]; Av[a][1] = W1 + dv[a][1]; Av[a][2] = W0 + dv[a][2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Bv[a][k] = Av[a][k] + Dv[a][k];
+    }
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int kx = Lat<D>::c(i, 0) + 1, ky = Lat<D>::c(i, 1) + 1, kz = Lat<D>::c(i, 2) + 1;
+        constexpr C Wx = kx == 1 ? W1 : W0, Wy = ky == 1 ? W1 : W0;
+        constexpr C wi = C(weight<D>(i));
+        C eqd, fsd;
+        if constexpr (D == 2) {
+            eqd = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
+            fsd = Dv[0][kx] * Bv[1][ky] + Av[0][kx] * Dv[1][ky];
+        } else {
+            eqd = dv[0][kx] * Av[1][ky] * Av[2][kz] + Wx * dv[1][ky] * Av[2][kz] + Wx * Wy * dv[2][kz];
+            fsd = Dv[0][kx] * Bv[1][ky] * Bv[2][kz] + Av[0][kx] * Dv[1][ky] * Bv[2][kz] +
+                  Av[0][kx] * Av[1][ky] * Dv[2][kz];
+        }
+        if constexpr (i != 0) {
+            const C heq = drho * wi + rho * eqd;
+            h[i] = h[i] + omega * (heq - h[i]) + rho * fsd;
+        }
+    });
+    // The update conserves mass exactly (sum heq = drho, sum of the source term = 0), but
+    // the rounded weights of the storage precision do not sum to one; taking the rest
+    // population as the remainder keeps the per-node mass error an unbiased rounding.
+    C rest = drho;
+    static_for<1, Lat<D>::Q>([&](auto I) { rest -= h[decltype(I)::value]; });
+    h[0] = rest;
+}
+
+}  // namespace lbm

@@ -17,6 +17,7 @@
 
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "step_common.hpp"
 
 namespace lbm {
 
@@ -25,124 +26,6 @@ namespace {
 constexpr int TX = 64;   // tile width in x: one wave64 row, coalesced 256 B (FP32) loads
 constexpr int TY = 4;    // tile height in y: 4 waves per workgroup
 constexpr int HALO = 2;  // two neighbour rings
-
-__device__ __forceinline__ int wrapi(int v, int n) {
-    if ((unsigned)v < (unsigned)n) return v;
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
-template <class C> __device__ __forceinline__ C omega_of(const Params<C> &p, C rho) {
-    if (!p.var_visc) return p.omega_l;
-    C s = (rho - p.rho_v) / (p.rho_l - p.rho_v);
-    s = s < C(0) ? C(0) : (s > C(1) ? C(1) : s);
-    C nu = p.nu_v + (p.nu_l - p.nu_v) * s;
-    return C(1) / (C(3) * nu + C(0.5));
-}
-
-// wrapped neighbour coordinates of (x, y, z): xs[k] = x + k - 1, ro[j][l] = row offset of (y + j - 1, z + l - 1)
-template <int D> struct Nbr {
-    int xs[3];
-    int ro[3][3];
-    __device__ __forceinline__ Nbr(const Geom &g, int x, int y, int z) {
-        xs[0] = wrapi(x - 1, g.nx); xs[1] = x; xs[2] = wrapi(x + 1, g.nx);
-        int ys[3] = {wrapi(y - 1, g.ny), y, wrapi(y + 1, g.ny)};
-        if constexpr (D == 3) {
-            int zs[3] = {wrapi(z - 1, g.nz), z, wrapi(z + 1, g.nz)};
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * (ys[j] + g.ny * zs[l]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * ys[j];
-        }
-    }
-    // node index of r + k*c for k = +-1
-    __device__ __forceinline__ int at(int dx, int dy, int dz) const { return xs[1 + dx] + ro[1 + dy][1 + dz]; }
-};
-
-// pull gather of the Q populations arriving at node n (= r) at this time step
-template <int D, class S, class C, bool MASK>
-__device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, const uint8_t *__restrict__ mask,
-                                       const Nbr<D> &nb, int n, C (&h)[Lat<D>::Q]) {
-    static_for<0, Lat<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
-        if constexpr (i == 0) {
-            h[0] = C(A[n]);
-        } else {
-            const int s = nb.at(-cx, -cy, -cz);
-            if constexpr (MASK) {
-                h[i] = mask[s] ? C(A[(long long)opp<D>(i) * qs + n]) : C(A[(long long)i * qs + s]);
-            } else {
-                h[i] = C(A[(long long)i * qs + s]);
-            }
-        }
-    });
-}
-
-// sum h and j = sum c h in a fixed order (pass 1 and pass 2 must agree bit for bit)
-template <int D, class C>
-__device__ __forceinline__ void moments_of(const C (&h)[Lat<D>::Q], C &sum, C (&j)[3]) {
-    sum = C(0);
-    j[0] = j[1] = j[2] = C(0);
-    static_for<0, Lat<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        sum += h[i];
-        static_for<0, D>([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            constexpr int ca = Lat<D>::c(i, a);
-            if constexpr (ca == 1) j[a] += h[i];
-            if constexpr (ca == -1) j[a] -= h[i];
-        });
-    });
-}
-
-// Product-form equilibrium and extended equilibrium in deviation form, then LBGK.
-// Per axis the triplet Psi_c(xi, zeta) = W_c + d_c with W = (1/6, 2/3, 1/6) for
-// c = (-1, 0, 1); the products are differenced by telescoping so no O(1) terms cancel.
-template <int D, class C>
-__device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const C (&u)[3], const C (&S)[3],
-                                        const C (&Phi)[3], C omega) {
-    constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
-    C dv[3][3], Av[3][3], Dv[3][3], Bv[3][3];
-    const C rinv = C(1) / rho;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const C ua = u[a], u2 = ua * ua;
-        dv[a][0] = C(0.5) * (u2 - ua);
-        dv[a][1] = -u2;
-        dv[a][2] = C(0.5) * (u2 + ua);
-        const C s = S[a] * rinv;                       // xi* - u
-        const C de = s * (C(2) * ua + s) + Phi[a] * rinv; // zeta* - zeta_eq
-        Dv[a][0] = C(0.5) * (de - s);
-        Dv[a][1] = -de;
-        Dv[a][2] = C(0.5) * (de + s);
-        Av[a][0] = W0 + dv[a][0]; Av[a][1] = W1 + dv[a][1]; Av[a][2] = W0 + dv[a][2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Bv[a][k] = Av[a][k] + Dv[a][k];
-    }
-    static_for<0, Lat<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int kx = Lat<D>::c(i, 0) + 1, ky = Lat<D>::c(i, 1) + 1, kz = Lat<D>::c(i, 2) + 1;
-        constexpr C Wx = kx == 1 ? W1 : W0, Wy = ky == 1 ? W1 : W0;
-        constexpr C wi = C(weight<D>(i));
-        C eqd, fsd;
-        if constexpr (D == 2) {
-            eqd = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
-            fsd = Dv[0][kx] * Bv[1][ky] + Av[0][kx] * Dv[1][ky];
-        } else {
-            eqd = dv[0][kx] * Av[1][ky] * Av[2][kz] + Wx * dv[1][ky] * Av[2][kz] + Wx * Wy * dv[2][kz];
-            fsd = Dv[0][kx] * Bv[1][ky] * Bv[2][kz] + Av[0][kx] * Dv[1][ky] * Bv[2][kz] +
-                  Av[0][kx] * Av[1][ky] * Dv[2][kz];
-        }
-        const C heq = drho * wi + rho * eqd;
-        h[i] = h[i] + omega * (heq - h[i]) + rho * fsd;
-    });
-}
 
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -214,11 +97,18 @@ template <int D> struct Tile {
     static constexpr int LS = LX * LY * LZ;
 };
 
-template <int D, class S, class C, bool MASK, bool OUT>
+enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2 };
+
+// MODE_STEP: one collide-stream step A -> B.
+// MODE_OUT:  rho and U = u + S/(2 rho) of the state in A, FP64, into out_rho / out_U.
+// MODE_INIT: equilibrium of the density in rho_f and the flow velocity U0 (= out_U, may be
+//            NULL): bare u = U0 - S/(2 rho), written into B in pull layout.
+template <int D, class S, class C, bool MASK, int MODE>
 __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                  const uint8_t *__restrict__ mask, Params<C> p,
                                                  const C *__restrict__ rho_f, const C *__restrict__ gf,
                                                  double *__restrict__ out_rho, double *__restrict__ out_U) {
+    constexpr bool OUT = MODE == MODE_OUT;
     using T = Tile<D>;
     __shared__ C s_rho[T::LS];
     __shared__ C s_psi[T::LS];
@@ -272,6 +162,32 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
 
         Nbr<D> nb(g, x, y, z);
         C h[Lat<D>::Q];
+        if constexpr (MODE == MODE_INIT) {
+            C u[3] = {C(0), C(0), C(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                u[a] = (out_U ? C(out_U[(long long)a * g.N + n]) : C(0)) - Sf[a] / (C(2) * rho);
+#pragma unroll
+            for (int i = 0; i < Lat<D>::Q; ++i) h[i] = C(0);
+            // omega = 1 with no source and no correction returns the equilibrium deviation
+            const C zero3[3] = {C(0), C(0), C(0)};
+            collide<D, C>(h, rho, rho - p.rho_ref, u, zero3, zero3, C(1));
+            static_for<0, Lat<D>::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+                if constexpr (i == 0) {
+                    B[n] = S(h[0]);
+                } else {
+                    // pulled at n from n - c_i, or from opp(i) at n when n - c_i is solid
+                    const int src = nb.at(-cx, -cy, -cz);
+                    if (MASK && mask[src])
+                        B[(long long)opp<D>(i) * g.qs + n] = S(h[i]);
+                    else
+                        B[(long long)i * g.qs + src] = S(h[i]);
+                }
+            });
+            continue;
+        } else {
         gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h);
         C drho, j[3];
         moments_of<D, C>(h, drho, j);
@@ -298,43 +214,18 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
                 B[(long long)i * g.qs + n] = S(h[i]);
             });
         }
+        }
     }
 }
 
 // ------------------------------------------------------------------ init
-template <int D, class S, class C, bool MASK>
-__global__ __launch_bounds__(256) void k_init(S *__restrict__ A, Geom g, const uint8_t *__restrict__ mask, Params<C> p,
-                                              const double *__restrict__ rho0, const double *__restrict__ u0) {
+// density field of the initial state in compute precision; solid nodes carry rho_w
+template <class C, bool MASK>
+__global__ __launch_bounds__(256) void k_prep_rho(C *__restrict__ rho_f, const double *__restrict__ rho0,
+                                                  const uint8_t *__restrict__ mask, C rho_w, int N) {
     const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= g.N) return;
-    if (MASK && mask[n]) return;
-    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
-    const C rho = C(rho0[n]);
-    C u[3] = {C(0), C(0), C(0)};
-    if (u0)
-#pragma unroll
-        for (int a = 0; a < D; ++a) u[a] = C(u0[(long long)a * g.N + n]);
-    C h[Lat<D>::Q];
-#pragma unroll
-    for (int i = 0; i < Lat<D>::Q; ++i) h[i] = C(0);
-    // with omega = 1, S = 0, Phi = 0 the update returns exactly the equilibrium deviation
-    const C zero3[3] = {C(0), C(0), C(0)};
-    collide<D, C>(h, rho, rho - p.rho_ref, u, zero3, zero3, C(1));
-    Nbr<D> nb(g, x, y, z);
-    static_for<0, Lat<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
-        if constexpr (i == 0) {
-            A[n] = S(h[0]);
-        } else {
-            // pulled at n from n - c_i, or from opp(i) at n when n - c_i is solid
-            const int s = nb.at(-cx, -cy, -cz);
-            if (MASK && mask[s])
-                A[(long long)opp<D>(i) * g.qs + n] = S(h[i]);
-            else
-                A[(long long)i * g.qs + s] = S(h[i]);
-        }
-    });
+    if (n >= N) return;
+    rho_f[n] = (MASK && mask[n]) ? rho_w : C(rho0[n]);
 }
 
 template <class S> __global__ __launch_bounds__(256) void k_fill_zero(S *__restrict__ A, long long count) {
@@ -367,32 +258,36 @@ dim3 moment_grid(int D, const Geom &g) {
 }
 
 template <int D, class S, class C, bool MASK> struct Launch {
+    static dim3 collide_grid(const Geom &g) {
+        return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? (g.nz + Tile<D>::ZB - 1) / Tile<D>::ZB : 1);
+    }
     static void fill_zero(hipStream_t s, void *A, long long count) {
         long long blocks = (count + 255) / 256;
         if (blocks > 65536) blocks = 65536;
         hipLaunchKernelGGL(k_fill_zero<S>, dim3((unsigned)blocks), dim3(256), 0, s, (S *)A, count);
     }
-    static void init(hipStream_t s, void *A, const Geom &g, const uint8_t *mask, const void *prm, const double *rho0,
-                     const double *u0) {
-        hipLaunchKernelGGL((k_init<D, S, C, MASK>), dim3((g.N + 255) / 256), dim3(256), 0, s, (S *)A, g, mask,
-                           *(const Params<C> *)prm, rho0, u0);
+    static void init(hipStream_t s, void *A, const Geom &g, const uint8_t *mask, const void *prm, void *rho,
+                     const double *rho0, const double *U0) {
+        const Params<C> &p = *(const Params<C> *)prm;
+        hipLaunchKernelGGL((k_prep_rho<C, MASK>), dim3((g.N + 255) / 256), dim3(256), 0, s, (C *)rho, rho0, mask,
+                           p.rho_w, g.N);
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_INIT>), collide_grid(g), dim3(256), 0, s,
+                           (const S *)nullptr, (S *)A, g, mask, p, (const C *)rho, (const C *)nullptr,
+                           (double *)nullptr, (double *)U0);
     }
     static void moments(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm, void *rho,
                         void *gfl, double *partials) {
         hipLaunchKernelGGL((k_moments<D, S, C, MASK>), moment_grid(D, g), dim3(256), 0, s, (const S *)A, g, mask,
                            *(const Params<C> *)prm, (C *)rho, (C *)gfl, partials);
     }
-    static dim3 collide_grid(const Geom &g) {
-        return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? (g.nz + Tile<D>::ZB - 1) / Tile<D>::ZB : 1);
-    }
     static void collide(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm,
                         const void *rho, const void *gfl) {
-        hipLaunchKernelGGL((k_collide<D, S, C, MASK, false>), collide_grid(g), dim3(256), 0, s, (const S *)A, (S *)B, g,
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_STEP>), collide_grid(g), dim3(256), 0, s, (const S *)A, (S *)B, g,
                            mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, nullptr, nullptr);
     }
     static void output(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm,
                        const void *rho, const void *gfl, double *orho, double *oU) {
-        hipLaunchKernelGGL((k_collide<D, S, C, MASK, true>), collide_grid(g), dim3(256), 0, s, (const S *)A,
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_OUT>), collide_grid(g), dim3(256), 0, s, (const S *)A,
                            (S *)nullptr, g, mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, orho, oU);
     }
     static KernelSet set() {

@@ -357,3 +357,19 @@ def test_laplace_law_static_drops():
     assert np.std(y / x) / np.mean(y / x) < 0.01        # Delta P * R_e constant
     assert abs(icpt) < 0.02 * y.max()
     assert 0.8 < slope / sigma < 1.25                   # W = 3: not yet thermodynamically converged
+
+
+def test_initial_state_reproduces_the_flow_velocity():
+    # lbm initial condition: f_eq(rho0, U0 - S/(2 rho0)); the moments then return U0 (Appendix D)
+    nx, ny, nz = 14, 12, 10
+    fl = T.Fluid(T.PR, 0.005, B21, 0.6, 1.0, 0.344)
+    rv, rl, _ = T.coexistence(fl)
+    rho, U = L.random_state(nx * ny * nz, 3, rv, rl, 0.05, 17)
+    cfg = O.Config(3, nx, ny, nz, T.PR, 0.005, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
+    r, U1, _ = O.Oracle(cfg).init(rho, U).moments()
+    assert np.abs(r - rho).max() < 1e-14 * rl
+    assert np.abs(U1 - U).max() < 1e-13
+    # the bare-velocity reading differs by the half force increment
+    cfg.variant = O.VARIANT_INIT_BARE_U
+    _, U2, _ = O.Oracle(cfg).init(rho, U).moments()
+    assert np.abs(U2 - U).max() > 1e-3
