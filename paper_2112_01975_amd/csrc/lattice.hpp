@@ -59,24 +59,39 @@ __host__ __device__ __forceinline__ void static_for(F &&f) {
 // ---------------------------------------------------------------- EOS (Sec. 3.1)
 enum { EOS_VDW = 0, EOS_PR = 1, EOS_RKS = 2, EOS_CS = 3, EOS_IDEAL = 4 };
 
+// Reciprocal and square root in compute precision: FP32 uses the hardware
+// v_rcp_f32 / v_sqrt_f32 (1 ulp); FP64 keeps the correctly rounded operations.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_c(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_c(double x) { return sqrt(x); }
+
 template <class C> struct Eos {
     int kind;
     C RT;   // R * T with T = T_reduced * Tc
     C aa;   // a * alpha(T) (alpha = 1 for vdW and CS)
     C b;
 
+    // P(rho) with a single reciprocal of the combined denominator
     __device__ __forceinline__ C pressure(C r) const {
         const C one = C(1);
+        const C m = one - b * r;
         switch (kind) {
-        case EOS_VDW: return r * RT / (one - b * r) - aa * r * r;
-        case EOS_PR: return r * RT / (one - b * r) - aa * r * r / (one + C(2) * b * r - b * b * r * r);
-        case EOS_RKS: return r * RT / (one - b * r) - aa * r * r / (one + b * r);
-        case EOS_CS: {
-            C e = C(0.25) * b * r;
-            C m = one - e;
-            return r * RT * (one + e + e * e - e * e * e) / (m * m * m) - aa * r * r;
+        case EOS_VDW: return r * RT * rcp(m) - aa * r * r;
+        case EOS_PR: {
+            const C q = one + C(2) * b * r - b * b * r * r;
+            return (r * RT * q - aa * r * r * m) * rcp(m * q);
         }
-        default: return r / C(3);
+        case EOS_RKS: {
+            const C q = one + b * r;
+            return (r * RT * q - aa * r * r * m) * rcp(m * q);
+        }
+        case EOS_CS: {
+            const C e = C(0.25) * b * r;
+            const C me = one - e;
+            return r * RT * (one + e + e * e - e * e * e) * rcp(me * me * me) - aa * r * r;
+        }
+        default: return r * C(1.0 / 3.0);
         }
     }
     // largest admissible density (repulsive pole); infinity for the ideal gas
@@ -91,8 +106,8 @@ template <class C> struct Eos {
 // signed pseudo-potential s*psi with psi = sqrt|P - P0|, P0 = rho/3, s = +1 iff P > P0
 // (eq force_form); neighbours use |s psi|, the centre its sign.
 template <class C> __device__ __forceinline__ C signed_psi(const Eos<C> &e, C r) {
-    C d = e.pressure(r) - r / C(3);
-    C s = sqrt(fabs(d));
+    C d = e.pressure(r) - r * C(1.0 / 3.0);
+    C s = sqrt_c(fabs(d));
     return d > C(0) ? s : -s;
 }
 

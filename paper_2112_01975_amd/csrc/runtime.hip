@@ -134,11 +134,18 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     c->ks = kernel_set(c->D, c->fp64, c->masked);
     c->nblk = moment_block_count(c->D, c->g);
     // single-pass z-march for D3Q27 (LBM2P_TWO_PASS=1 forces the two-pass step;
-    // LBM2P_FUSED_TY / LBM2P_FUSED_TZ override the tile height and z-chunk length)
+    // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length)
     if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
-        const int ty = env_int("LBM2P_FUSED_TY", 8), tz = env_int("LBM2P_FUSED_TZ", 32);
-        c->fused = fused_launcher(c->fp64, c->masked, ty);
-        if (c->fused) c->fg = fused_grid(c->g, ty, tz > 0 ? tz : 32);
+        const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
+        const int tz = env_int("LBM2P_FUSED_TZ", 128);
+        const unsigned long long bytes = (unsigned long long)c->Q * (unsigned long long)c->g.qs * c->sbytes;
+        if (bytes < 0xFFFFFFFFull) {   // one buffer resource addresses the whole lattice
+            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, env_int("LBM2P_FUSED_QUEUE", 1) != 0);
+            if (c->fused) {
+                c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
+                c->fg.pop_bytes = (unsigned)bytes;
+            }
+        }
     }
     const size_t N = (size_t)c->g.N;
     const size_t cbytes = c->fp64 ? 8 : 4;

@@ -20,7 +20,7 @@ template <class C> __device__ __forceinline__ C omega_of(const Params<C> &p, C r
     C s = (rho - p.rho_v) / (p.rho_l - p.rho_v);
     s = s < C(0) ? C(0) : (s > C(1) ? C(1) : s);
     C nu = p.nu_v + (p.nu_l - p.nu_v) * s;
-    return C(1) / (C(3) * nu + C(0.5));
+    return rcp(C(3) * nu + C(0.5));
 }
 
 // wrapped neighbour coordinates of (x, y, z): xs[k] = x + k - 1, ro[j][l] = row offset of (y + j - 1, z + l - 1)
@@ -43,9 +43,30 @@ template <int D> struct Nbr {
                 for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * ys[j];
         }
     }
+    // from per-axis wrapped coordinates already multiplied out: xs = x-1, x, x+1;
+    // ry = nx * (y-1, y, y+1); pz = nx * ny * (z-1, z, z+1)
+    __device__ __forceinline__ Nbr(const int (&xs_)[3], const int (&ry)[3], const int (&pz)[3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[k] = xs_[k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) ro[j][l] = ry[j] + pz[l];
+    }
     // node index of r + k*c for k = +-1
     __device__ __forceinline__ int at(int dx, int dy, int dz) const { return xs[1 + dx] + ro[1 + dy][1 + dz]; }
 };
+
+// Element idx of the array that starts at `base`, addressed as a uniform 64-bit base plus
+// a 32-bit byte offset: the compiler then issues global loads/stores with an SGPR base
+// and one VGPR offset (saddr form) instead of a 64-bit address per lane. Every
+// population array is smaller than 4 GiB (checked when a context is created).
+template <class T> __device__ __forceinline__ T ld_at(const T *__restrict__ base, unsigned idx) {
+    return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
+}
+template <class T> __device__ __forceinline__ void st_at(T *__restrict__ base, unsigned idx, T v) {
+    *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
+}
 
 // pull gather of the Q populations arriving at node n (= r) at this time step
 template <int D, class S, class C, bool MASK>
@@ -55,13 +76,61 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, co
         constexpr int i = decltype(I)::value;
         constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
         if constexpr (i == 0) {
-            h[0] = C(A[n]);
+            h[0] = C(ld_at(A, (unsigned)n));
         } else {
-            const int s = nb.at(-cx, -cy, -cz);
+            const unsigned s = (unsigned)nb.at(-cx, -cy, -cz);
             if constexpr (MASK) {
-                h[i] = mask[s] ? C(A[(long long)opp<D>(i) * qs + n]) : C(A[(long long)i * qs + s]);
+                h[i] = ld_at(mask, s) ? C(ld_at(A + opp<D>(i) * qs, (unsigned)n)) : C(ld_at(A + i * qs, s));
             } else {
-                h[i] = C(A[(long long)i * qs + s]);
+                h[i] = C(ld_at(A + i * qs, s));
+            }
+        }
+    });
+}
+
+
+// Population array through one buffer resource: 128-bit descriptor in SGPRs, byte offset
+// of the node in a VGPR, byte offset of population i (i * qs * sizeof(S)) as the scalar
+// offset. Hardware range checking returns 0 for reads and drops writes beyond `bytes`.
+// Requires the whole array (Q * qs * sizeof(S)) to be below 4 GiB.
+template <class S> struct PopBuf {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned qsb;   // qs * sizeof(S)
+    __device__ __forceinline__ PopBuf(const S *base, long long qs, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0, (int)bytes, 0x00020000)),
+          qsb((unsigned)(qs * (long long)sizeof(S))) {}
+    __device__ __forceinline__ S load(int i, unsigned node) const;
+    __device__ __forceinline__ void store(int i, unsigned node, S v) const;
+};
+template <> __device__ __forceinline__ float PopBuf<float>::load(int i, unsigned node) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, node * 4u, (unsigned)i * qsb, 0));
+}
+template <> __device__ __forceinline__ void PopBuf<float>::store(int i, unsigned node, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, node * 4u, (unsigned)i * qsb, 0);
+}
+template <> __device__ __forceinline__ double PopBuf<double>::load(int i, unsigned node) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, node * 8u, (unsigned)i * qsb, 0));
+}
+template <> __device__ __forceinline__ void PopBuf<double>::store(int i, unsigned node, double v) const {
+    using u2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, node * 8u, (unsigned)i * qsb, 0);
+}
+
+// pull gather through a buffer resource (same semantics as gather())
+template <int D, class S, class C, bool MASK>
+__device__ __forceinline__ void gather_buf(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Nbr<D> &nb,
+                                           int n, C (&h)[Lat<D>::Q]) {
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        if constexpr (i == 0) {
+            h[0] = C(A.load(0, (unsigned)n));
+        } else {
+            const unsigned s = (unsigned)nb.at(-cx, -cy, -cz);
+            if constexpr (MASK) {
+                h[i] = ld_at(mask, s) ? C(A.load(opp<D>(i), (unsigned)n)) : C(A.load(i, s));
+            } else {
+                h[i] = C(A.load(i, s));
             }
         }
     });
@@ -93,7 +162,7 @@ __device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const 
                                         const C (&Phi)[3], C omega) {
     constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
     C dv[3][3], Av[3][3], Dv[3][3], Bv[3][3];
-    const C rinv = C(1) / rho;
+    const C rinv = rcp(rho);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const C ua = u[a], u2 = ua * ua;

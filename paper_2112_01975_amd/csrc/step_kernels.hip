@@ -70,9 +70,10 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g
             C sum, j[3];
             moments_of<D, C>(h, sum, j);
             rho = p.rho_ref + sum;
+            const C rinv = rcp(rho);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const C ua = j[a] / rho;
+                const C ua = j[a] * rinv;
                 ga[a] = rho * ua * ua * ua;
             }
             v[0] = double(rho);
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             C u[3] = {C(0), C(0), C(0)};
 #pragma unroll
             for (int a = 0; a < D; ++a)
-                u[a] = (out_U ? C(out_U[(long long)a * g.N + n]) : C(0)) - Sf[a] / (C(2) * rho);
+                u[a] = (out_U ? C(out_U[(long long)a * g.N + n]) : C(0)) - Sf[a] * (C(0.5) * rcp(rho));
 #pragma unroll
             for (int i = 0; i < Lat<D>::Q; ++i) h[i] = C(0);
             // omega = 1 with no source and no correction returns the equilibrium deviation
@@ -192,8 +193,9 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         C drho, j[3];
         moments_of<D, C>(h, drho, j);
         C u[3] = {C(0), C(0), C(0)};
+        const C rinv = rcp(rho);
 #pragma unroll
-        for (int a = 0; a < D; ++a) u[a] = j[a] / rho;
+        for (int a = 0; a < D; ++a) u[a] = j[a] * rinv;
         const C omega = omega_of(p, rho);
         C Phi[3] = {C(0), C(0), C(0)};
         {
@@ -206,12 +208,12 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         if constexpr (OUT) {
             out_rho[n] = double(rho);
 #pragma unroll
-            for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = double(u[a] + Sf[a] / (C(2) * rho));
+            for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = double(u[a] + Sf[a] * (C(0.5) * rinv));
         } else {
             collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
             static_for<0, Lat<D>::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                B[(long long)i * g.qs + n] = S(h[i]);
+                st_at(B + i * g.qs, (unsigned)n, S(h[i]));
             });
         }
         }

@@ -216,3 +216,23 @@ def test_watchdog_reports_divergence_and_domain():
         with pytest.raises(P.LbmError) as ei:
             s.init(np.full(case.N, 1.0 / case.b + 1.0))   # b rho >= 1
         assert ei.value.code == P.LBM_E_DOMAIN
+
+
+@pytest.mark.parametrize("dims,masked", [((70, 36, 40), False), ((64, 8, 32), False), ((5, 3, 7), False),
+                                         ((48, 20, 36), True)])
+def test_fused_step_matches_two_pass_fp32(dims, masked, monkeypatch):
+    # the single-pass z-march (default for D3Q27 FP32) against the two-pass step, same inputs:
+    # ragged x / y tiles, several z-chunks with a ragged last chunk, tiny grids, a solid mask
+    nx, ny, nz = dims
+    mask = L.pillar_mask(nx, ny, nz, 4, 4, 5) if masked else None
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6,
+                rho_wall=0.0102306 if masked else 0.0, mask=mask)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(nx, ny, nz, min(nx, ny, nz) / 4, rl, rv, 5.0, noise=1e-5, seed=1007)
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "16")
+    fused = run_gpu(case, rho0, None, 30, precision=1, rho_ref=rv)
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    two = run_gpu(case, rho0, None, 30, precision=1, rho_ref=rv)
+    assert np.all(np.isfinite(fused[0]))
+    assert max_rel(fused[0], two[0]) < 1e-5
+    assert np.abs(fused[1] - two[1]).max() < 1e-6
