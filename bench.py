@@ -3,20 +3,23 @@
 
 Workload (synthetic, shaped like the paper's 3D drop tests): Peng-Robinson EOS,
 acentric factor 0.344, T/Tc = 0.6 (liquid/vapour density ratio 853), b = 2/21,
-kappa~ = 0.02 and a chosen so that the flat equilibrium interface is 5 nodes wide,
-drop radius 50 at the centre with a tanh profile of width 5 between the Maxwell
-densities, multiplicative density noise 1e-5 (seed 1003), tau = 0.8, periodic.
+kappa~ = 0.02 with `a` chosen so that the flat equilibrium interface is 5 nodes
+wide, drop radius 50 at the centre with a tanh profile of width 5 between the
+Maxwell densities, multiplicative density noise 1e-5 (seed 1003), at rest,
+tau = 0.8, periodic.
 
 Timed: K steps of lbm_step with the state resident in HBM, bracketed by device
-synchronisation. One JSON line on stdout. The FP32 leg stores populations as
-FP32 deviations from w_i rho_v; the FP64 leg is reported alongside, with the
-maximum relative density difference between the two after the same steps.
+synchronisation; one JSON line on stdout. The headline leg stores populations
+as FP32 deviations from w_i rho_v (single-pass z-march kernel); the FP64 leg runs
+the same workload and the line states the density difference between the two
+after the same number of steps. `roofline` is for the dominant kernel: algorithmic
+bytes per launch (27 populations read and written, 4 B each, per node) over its
+average launch time from HIP events on the launch stream.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -28,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor peak
 B21 = 2.0 / 21.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused3_d3q27_256_fp32_traffic.txt")
 
 
 def log(msg):
@@ -35,47 +39,64 @@ def log(msg):
 
 
 def workload(P, n, precision, check_every=-1):
-    """Params and initial fields of the static-drop workload at n^3."""
+    """Params and initial density of the static-drop workload at n^3."""
     base = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
-    k_ref = P.lbm_kappa_for_width(base, 5.0)          # kappa(W=5) scales linearly with a
-    a = base.a * 0.02 / k_ref
+    a = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)   # kappa(W) is linear in a at fixed b, T/Tc
     p = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_PR, a, B21, 1.0, 0.344, 0.6, 0.02, 0.8,
                  precision=precision, check_every=check_every)
     rv, rl, _, _ = P.lbm_coexistence(p)
     p.rho_ref = rv if precision == P.LBM_FP32_DEV else 0.0
     import lbm_inputs as L
-    radius = 50.0 * n / 256.0
-    rho0 = L.drop(n, n, n, radius, rl, rv, 5.0, noise=1e-5, seed=1003)
+    rho0 = L.drop(n, n, n, 50.0 * n / 256.0, rl, rv, 5.0, noise=1e-5, seed=1003)
     return p, rho0, (rv, rl, a)
 
 
 def time_leg(P, torch, n, precision, steps, warmup):
-    p, rho0, (rv, rl, a) = workload(P, n, precision)
+    p, rho0, meta = workload(P, n, precision)
     sim = P.Simulation(p)
     sim.init(rho0)
-    stream = torch.cuda.current_stream()
-    P.lbm_set_stream(sim.ctx, stream.cuda_stream)
+    _, _, tot0 = sim.moments(want_fields=False)
+    P.lbm_set_stream(sim.ctx, torch.cuda.current_stream().cuda_stream)
     P.lbm_step(sim.ctx, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.lbm_step(sim.ctx, steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-kernel device time from HIP events on the same stream
     kt = max(5, min(steps, 20))
-    ms, nl = P.lbm_step_timed(sim.ctx, kt)
-    N = n ** 3
-    s = 4 if precision == P.LBM_FP32_DEV else 8
-    Q, D = 27, 3
-    res = {
-        "mlups": N * steps / dt / 1e6,
-        "ms_per_step": dt * 1e3 / steps,
-        "kernel_ms": {"moments": ms[0] / nl[0], "collide": ms[1] / nl[1]},
-        "bytes_min_per_lup": 2 * Q * s,
-        "bytes_collide_per_lup": (2 * Q + D + 1) * s,
-        "steps_total": warmup + steps + kt,
-    }
-    return sim, res, (rv, rl, a)
+    ms, nl = P.lbm_step_timed(sim.ctx, kt)   # HIP events around every launch
+    kern = {"moment_pass": ms[0] / nl[0] if nl[0] else 0.0, "step_kernel": ms[1] / nl[1]}
+    return sim, {"mlups": n ** 3 * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps, "kernel_ms": kern,
+                 "fused": nl[0] == 0, "steps_total": warmup + steps + kt, "mass0": tot0[0]}, meta
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=5):
+    """Plain device copy of known size: attainable bandwidth (and the counter scale in profiles)."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return {"bytes_per_copy": 2 * nbytes, "GBs": 2 * nbytes / t / 1e9}
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the fused kernel from the committed counter summary, if it
+    was taken on the current kernel sources; otherwise None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    from paper_2112_01975_amd import profsum
+    d = profsum.read_traffic(TRAFFIC_SUMMARY)
+    if d.get("source_fingerprint") != profsum.source_fingerprint():
+        return None
+    return float(d["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(budget_s=12.0):
@@ -97,8 +118,8 @@ def cpu_baseline(budget_s=12.0):
         steps += 2
     dt = time.perf_counter() - t0
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"D3Q27 {n}^3 drop (same EOS, T/Tc, kappa, tau; radius scaled), {steps} FP64 steps, "
-                      f"{dt:.1f} s"}
+            "sample": f"D3Q27 {n}^3 drop (same EOS, T/Tc, kappa, tau; radius scaled to 9.4), {steps} FP64 "
+                      f"steps in {dt:.1f} s"}
 
 
 def main():
@@ -111,7 +132,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: the step runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -122,29 +143,41 @@ def main():
         sys.exit(1)
     n = args.size
     N = n ** 3
-    log(f"[bench] FP32-dev leg {n}^3 warmup={args.warmup} steps={args.steps}")
+    log(f"[bench] FP32 deviation-storage leg {n}^3 warmup={args.warmup} steps={args.steps}")
     sim32, r32, (rv, rl, a) = time_leg(P, torch, n, P.LBM_FP32_DEV, args.steps, args.warmup)
-    log(f"[bench] FP32-dev {r32['mlups']:.0f} MLUPS, kernels {r32['kernel_ms']}")
+    log(f"[bench] FP32 {r32['mlups']:.0f} MLUPS, kernels {r32['kernel_ms']}")
+    probe = copy_probe(torch)
+    log(f"[bench] copy probe {probe['GBs']:.0f} GB/s")
     fp64 = None
-    dens_err = None
+    dens = None
+    rho32, _, t32 = sim32.moments()
     if not args.no_fp64:
         log("[bench] FP64 leg")
         sim64, r64, _ = time_leg(P, torch, n, P.LBM_FP64, args.steps, args.warmup)
         log(f"[bench] FP64 {r64['mlups']:.0f} MLUPS, kernels {r64['kernel_ms']}")
-        rho32, _, t32 = sim32.moments()
         rho64, _, t64 = sim64.moments()
-        dens_err = float(np.max(np.abs(rho32 - rho64) / rho64))
-        t_c = r64["kernel_ms"]["collide"] * 1e-3
+        c = n // 2
+        r3a, r3b = rho32.reshape(n, n, n), rho64.reshape(n, n, n)
+        dens = {"after_steps": r32["steps_total"],
+                "max_pointwise_rel": float(np.max(np.abs(rho32 - rho64) / rho64)),
+                "liquid_centre_rel": float(abs(r3a[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
+                                               / r3b[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean() - 1)),
+                "vapour_corner_rel": float(abs(r3a[:4, :4, :4].mean() / r3b[:4, :4, :4].mean() - 1))}
+        t_k = r64["kernel_ms"]["step_kernel"] * 1e-3
+        b64 = (2 * 27 + 4) * 8 if not r64["fused"] else 2 * 27 * 8
         fp64 = {"value": r64["mlups"], "unit": "MLUPS", "ms_per_step": r64["ms_per_step"],
-                "roofline": {"bound": "hbm", "achieved": N * r64["bytes_collide_per_lup"] / t_c / 1e9,
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s"},
-                "useful_frac_step": r64["mlups"] * 1e6 * r64["bytes_min_per_lup"] / (HBM_PEAK_GBS * 1e9),
-                "mass_rel_diff_vs_fp32": abs(t32[0] - t64[0]) / t64[0]}
-        fp64["roofline"]["frac"] = fp64["roofline"]["achieved"] / HBM_PEAK_GBS
+                "kernel": "collide-stream pass (two-pass step)" if not r64["fused"] else "fused step",
+                "kernel_ms": r64["kernel_ms"],
+                "roofline": {"bound": "hbm", "achieved": N * b64 / t_k / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": N * b64 / t_k / 1e9 / HBM_PEAK_GBS, "bytes_per_lup": b64},
+                "useful_frac_step": r64["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9),
+                "mass_rel_drift": abs(t64[0] / r64["mass0"] - 1)}
         sim64.close()
     sim32.close()
-    t_c = r32["kernel_ms"]["collide"] * 1e-3
-    achieved = N * r32["bytes_collide_per_lup"] / t_c / 1e9
+    t_k = r32["kernel_ms"]["step_kernel"] * 1e-3
+    bytes_lup = 2 * 27 * 4
+    achieved = N * bytes_lup / t_k / 1e9
+    traffic = traffic_from_profile() if r32["fused"] else None
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -154,18 +187,20 @@ def main():
         "value": r32["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r32["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"D3Q27 {n}^3 periodic static drop R={50 * n // 256}, Peng-Robinson "
+        "config": {"workload": f"D3Q27 {n}^3 periodic static drop R={50 * n / 256:g} at rest, Peng-Robinson "
                                f"omega'=0.344 T/Tc=0.6 (rho_l/rho_v={rl / rv:.0f}), kappa=0.02, a={a:.6g}, "
-                               f"b=2/21, W=5, tau=0.8, FP32 deviation storage rho_ref=rho_v",
-                   "nodes": N, "lattice": "D3Q27", "precision": "fp32-dev"},
+                               f"b=2/21, W=5, tau=0.8, FP32 deviation storage (rho_ref=rho_v)",
+                   "nodes": N, "lattice": "D3Q27", "precision": "fp32-deviation", "kernel": "fused z-march"
+                   if r32["fused"] else "two-pass"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "collide-stream pass",
-                     "bytes_per_lup": r32["bytes_collide_per_lup"]},
-        "useful_frac_step": r32["mlups"] * 1e6 * r32["bytes_min_per_lup"] / (HBM_PEAK_GBS * 1e9),
-        "kernel_ms": r32["kernel_ms"],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fused3 (single-pass step)" if r32["fused"] else "collide-stream pass",
+                     "bytes_per_lup": bytes_lup, "launch_ms": r32["kernel_ms"]["step_kernel"]},
+        "useful_frac_step": r32["mlups"] * 1e6 * bytes_lup / (HBM_PEAK_GBS * 1e9),
+        "attainable_copy_GBs": probe["GBs"],
+        "mass_rel_drift_fp32": abs(t32[0] / r32["mass0"] - 1),
+        "density_error_fp32_vs_fp64": dens,
         "fp64": fp64,
-        "density_error_fp32_vs_fp64": dens_err,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

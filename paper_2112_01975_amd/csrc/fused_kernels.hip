@@ -90,6 +90,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     // QUEUE: the populations this thread pulled for planes z, z+1, z+2 stay in registers
     // until plane z is collided (no second pull); otherwise they are pulled again.
     C q0[27], q1[27], q2[27];
+    C m0[4], m1[4], m2[4];   // QUEUE: (sum h, j) of the queued planes
 
 #pragma unroll 1
     for (int k = -4; k < fg.tz; ++k) {
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 gather_buf<3, S, C, MASK>(Ab, mask, Nbr<3>(ixs, iry, pl), n, h);
                 C sum, j[3];
                 moments_of<3, C>(h, sum, j);
+                m2[0] = sum; m2[1] = j[0]; m2[2] = j[1]; m2[3] = j[2];
                 rho = p.rho_ref + sum;
                 const C rinv = rcp(rho);
 #pragma unroll
@@ -181,14 +183,15 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
 #pragma unroll
                 for (int a = 0; a < 3; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
                 C h[27];
+                C drho, j[3];
                 if constexpr (QUEUE) {
 #pragma unroll
                     for (int i = 0; i < 27; ++i) h[i] = q0[i];
+                    drho = m0[0]; j[0] = m0[1]; j[1] = m0[2]; j[2] = m0[3];
                 } else {
                     gather_buf<3, S, C, MASK>(Ab, mask, Nbr<3>(ixs, iry, zpl), n, h);
+                    moments_of<3, C>(h, drho, j);
                 }
-                C drho, j[3];
-                moments_of<3, C>(h, drho, j);
                 const C rinv = rcp(rho);
                 C u[3];
 #pragma unroll
@@ -210,6 +213,8 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         if constexpr (QUEUE) {
 #pragma unroll
             for (int i = 0; i < 27; ++i) { q0[i] = q1[i]; q1[i] = q2[i]; }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { m0[i] = m1[i]; m1[i] = m2[i]; }
         }
     }
 }

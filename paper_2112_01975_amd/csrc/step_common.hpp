@@ -156,7 +156,12 @@ __device__ __forceinline__ void moments_of(const C (&h)[Lat<D>::Q], C &sum, C (&
 // Product-form equilibrium and extended equilibrium in deviation form, then LBGK.
 // drho = sum of the pre-collision deviations (the node's mass minus rho_ref).
 // Per axis the triplet Psi_c(xi, zeta) = W_c + d_c with W = (1/6, 2/3, 1/6) for
-// c = (-1, 0, 1); the products are differenced by telescoping so no O(1) terms cancel.
+// c = (-1, 0, 1); products are differenced by telescoping so no O(1) terms cancel:
+//   f_eq - w rho_ref = drho w + rho [prod(W + d) - prod W]
+//   f*   - f_eq      = rho [prod(W + d + D) - prod(W + d)]
+// with the x-y parts of both telescoped sums formed once per (c_x, c_y) pair.
+// The update f + omega (f_eq - f) + (f* - f_eq) is evaluated as
+//   (1 - omega) h + (omega drho) w + rho (omega eqd + fsd).
 template <int D, class C>
 __device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const C (&u)[3], const C (&S)[3],
                                         const C (&Phi)[3], C omega) {
@@ -169,8 +174,8 @@ __device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const 
         dv[a][0] = C(0.5) * (u2 - ua);
         dv[a][1] = -u2;
         dv[a][2] = C(0.5) * (u2 + ua);
-        const C s = S[a] * rinv;                       // xi* - u
-        const C de = s * (C(2) * ua + s) + Phi[a] * rinv; // zeta* - zeta_eq
+        const C s = S[a] * rinv;                           // xi* - u
+        const C de = s * (C(2) * ua + s) + Phi[a] * rinv;  // zeta* - zeta_eq
         Dv[a][0] = C(0.5) * (de - s);
         Dv[a][1] = -de;
         Dv[a][2] = C(0.5) * (de + s);
@@ -178,24 +183,32 @@ __device__ __forceinline__ void collide(C (&h)[Lat<D>::Q], C rho, C drho, const 
 #pragma unroll
         for (int k = 0; k < 3; ++k) Bv[a][k] = Av[a][k] + Dv[a][k];
     }
-    static_for<0, Lat<D>::Q>([&](auto I) {
+    // x-y factors: E = d_x A_y + W_x d_y, F = D_x B_y + A_x D_y, AA = A_x A_y
+    C E[3][3], F[3][3], AA[3][3];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const C Wx = kx == 1 ? W1 : W0;
+            E[kx][ky] = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
+            F[kx][ky] = Dv[0][kx] * Bv[1][ky] + Av[0][kx] * Dv[1][ky];
+            AA[kx][ky] = Av[0][kx] * Av[1][ky];
+        }
+    const C om1 = C(1) - omega, omd = omega * drho;
+    static_for<1, Lat<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int kx = Lat<D>::c(i, 0) + 1, ky = Lat<D>::c(i, 1) + 1, kz = Lat<D>::c(i, 2) + 1;
-        constexpr C Wx = kx == 1 ? W1 : W0, Wy = ky == 1 ? W1 : W0;
+        constexpr C WW = (kx == 1 ? W1 : W0) * (ky == 1 ? W1 : W0);
         constexpr C wi = C(weight<D>(i));
         C eqd, fsd;
         if constexpr (D == 2) {
-            eqd = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
-            fsd = Dv[0][kx] * Bv[1][ky] + Av[0][kx] * Dv[1][ky];
+            eqd = E[kx][ky];
+            fsd = F[kx][ky];
         } else {
-            eqd = dv[0][kx] * Av[1][ky] * Av[2][kz] + Wx * dv[1][ky] * Av[2][kz] + Wx * Wy * dv[2][kz];
-            fsd = Dv[0][kx] * Bv[1][ky] * Bv[2][kz] + Av[0][kx] * Dv[1][ky] * Bv[2][kz] +
-                  Av[0][kx] * Av[1][ky] * Dv[2][kz];
+            eqd = Av[2][kz] * E[kx][ky] + WW * dv[2][kz];
+            fsd = Bv[2][kz] * F[kx][ky] + AA[kx][ky] * Dv[2][kz];
         }
-        if constexpr (i != 0) {
-            const C heq = drho * wi + rho * eqd;
-            h[i] = h[i] + omega * (heq - h[i]) + rho * fsd;
-        }
+        h[i] = om1 * h[i] + omd * wi + rho * (omega * eqd + fsd);
     });
     // The update conserves mass exactly (sum heq = drho, sum of the source term = 0), but
     // the rounded weights of the storage precision do not sum to one; taking the rest

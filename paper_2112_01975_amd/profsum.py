@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+  python -m paper_2112_01975_amd.profsum stats <kernel_stats.csv> <command...>
+  python -m paper_2112_01975_amd.profsum traffic <fetch_counter_collection.csv> <write_counter_collection.csv> \
+         <kernel-substring> <copy-bytes> <command...>
+
+`stats` turns a --kernel-trace --stats summary into a short text table. `traffic`
+reads two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scales each
+counter by what it reads for the plain device copy of known size in the same run
+(the bench's copy probe), and prints HBM bytes per launch of the named kernel,
+together with a fingerprint of the kernel sources so that a later run can tell
+whether the counters still describe the current kernel.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/fused_kernels.hip", "csrc/step_common.hpp", "csrc/lattice.hpp", "csrc/step_kernels.hip",
+                  "csrc/kernels.hpp", "csrc/fused.hpp"]
+
+
+def source_fingerprint() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    m = re.search(r"(k_\w+|copyBuffer\w*|\w+Kernel\w*)", name)
+    base = m.group(1) if m else name[:40]
+    t = re.search(r"<([^()]*)>", name)
+    return f"{base}<{t.group(1)}>" if t and base.startswith("k_") else base
+
+
+def stats(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# rocprofv3 --kernel-trace --stats", f"# command: {command}", "",
+           f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_%':>8s}"]
+    for r in rows:
+        name = short_name(r["Name"])
+        calls = int(r["Calls"])
+        avg = float(r["AverageNs"]) / 1e3
+        mn = float(r["MinNs"]) / 1e3
+        mx = float(r["MaxNs"]) / 1e3
+        pct = float(r["Percentage"])
+        out.append(f"{name:60s} {calls:6d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {pct:8.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path: str):
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return acc
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, command: str) -> str:
+    f = _per_kernel(fetch_csv)
+    w = _per_kernel(write_csv)
+
+    def pick(d, key):
+        vals = [v for name, vs in d.items() if key in name for v in vs]
+        if not vals:
+            raise SystemExit(f"no dispatch matching {key!r}")
+        return vals
+
+    # copy probe: the largest copy dispatches move copy_bytes each way
+    cf = max(pick(f, "copyBuffer")) * 1024.0
+    cw = max(pick(w, "copyBuffer")) * 1024.0
+    fetch_scale = copy_bytes / cf
+    write_scale = copy_bytes / cw
+    kf = pick(f, kernel)
+    kw = pick(w, kernel)
+    fb = sum(kf) / len(kf) * 1024.0 * fetch_scale
+    wb = sum(kw) / len(kw) * 1024.0 * write_scale
+    lines = [
+        "# HBM traffic per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)",
+        f"# command: {command}",
+        f"kernel: {kernel}",
+        f"source_fingerprint: {source_fingerprint()}",
+        f"dispatches_fetch: {len(kf)}",
+        f"dispatches_write: {len(kw)}",
+        f"copy_probe_bytes: {copy_bytes}",
+        f"fetch_scale: {fetch_scale:.4f}",
+        f"write_scale: {write_scale:.4f}",
+        f"fetch_bytes_per_launch: {fb:.0f}",
+        f"write_bytes_per_launch: {wb:.0f}",
+        f"traffic_bytes_per_launch: {fb + wb:.0f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(path: str) -> dict:
+    d = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    return d
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        sys.stdout.write(stats(sys.argv[2], " ".join(sys.argv[3:])))
+    elif sys.argv[1] == "traffic":
+        sys.stdout.write(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), " ".join(sys.argv[6:])))
+    else:
+        raise SystemExit(__doc__)
