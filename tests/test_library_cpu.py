@@ -1,0 +1,76 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared entry point,
+its host-side thermodynamics agrees with the oracle's independent implementation,
+and parameter validation rejects bad problem statements before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lbm2p.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2112_01975_amd as P
+    lib = ctypes.CDLL(P.lbm.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), f"{name} not exported"
+    assert set(names) == set(P.lbm.EXPORTED)
+
+
+@pytest.mark.parametrize("eos,a,om,tr", [(0, 9 / 49, 0.0, 0.9), (0, 9 / 49, 0.0, 0.55), (1, 2 / 49, 0.344, 0.6),
+                                         (1, 2 / 49, 0.344, 0.5), (2, 0.01, 0.344, 0.7), (3, 0.01, 0.0, 0.7)])
+def test_host_coexistence_matches_oracle(eos, a, om, tr):
+    import paper_2112_01975_amd as P
+    p = P.Params(P.LBM_D3Q27, 4, 4, 4, eos, a, 2 / 21, 1.0, om, tr)
+    rv, rl, ps, Tt = P.lbm_coexistence(p)
+    fl = T.Fluid(eos, a, 2 / 21, tr, 1.0, om)
+    ov, ol, ops = T.coexistence(fl)
+    assert abs(rv / ov - 1) < 1e-10 and abs(rl / ol - 1) < 1e-10 and abs(ps / ops - 1) < 1e-9
+    assert abs(Tt / fl.T - 1) < 1e-15
+    k = P.lbm_kappa_for_width(p, 5.0)
+    assert abs(k / T.kappa_for_width(fl, 5.0) - 1) < 1e-8
+
+
+def test_no_loop_above_critical_temperature_is_a_domain_error():
+    import paper_2112_01975_amd as P
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_coexistence(P.Params(P.LBM_D2Q9, 4, 4, 1, P.LBM_EOS_VDW, 9 / 49, 2 / 21, T_reduced=1.05))
+    assert ei.value.code == P.LBM_E_DOMAIN
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(lattice=7), "lattice"),
+    (dict(nz=2), "nz == 1"),
+    (dict(nx=0), "grid sizes"),
+    (dict(tau_liquid=0.5), "tau_liquid"),
+    (dict(kappa=-0.1), "kappa"),
+    (dict(a=0.0), "EOS parameters"),
+    (dict(T_reduced=0.0), "T_reduced"),
+    (dict(precision=5), "precision"),
+    (dict(eos=9), "equation of state"),
+    (dict(tau_vapour=0.4), "tau_vapour"),
+    (dict(tau_vapour=0.9, rho_liquid=1.0, rho_vapour=2.0), "variable viscosity"),
+    (dict(mask=np.zeros(64 * 64, np.uint8), rho_wall=0.0), "rho_wall"),
+])
+def test_create_rejects_bad_parameters_without_gpu(bad, msg):
+    import paper_2112_01975_amd as P
+    kw = dict(lattice=P.LBM_D2Q9, nx=64, ny=64, nz=1)
+    kw.update(bad)
+    p = P.Params(**kw)
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_create(p)
+    assert ei.value.code == P.LBM_E_INVAL
+    assert msg in str(ei.value)
+    assert msg in P.lbm_last_error(None)
