@@ -99,6 +99,50 @@ def traffic_from_profile():
     return float(d["traffic_bytes_per_launch"])
 
 
+def batch_sweep(P, torch, steps):
+    """64 D2Q9 flat-interface cases, 4 x L with L log-spaced 128..2048 increasing with T/Tc in
+    0.55..0.99 (vdW, kappa 0.02, a set for W = 4 at T/Tc = 0.55, tau 0.8; FP32 below T/Tc = 0.95,
+    FP64 above): one persistent launch per chunk of steps (HIP graph) against the same cases
+    stepped one by one through lbm_step."""
+    import lbm_inputs as L
+    base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.55, 0.02, 0.8)
+    a = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
+    cases, inits = [], []
+    for sc in L.temperature_sweep(64, 0.55, 0.99, 128, 2048, 4):
+        prec = P.LBM_FP64 if sc.fp64 else P.LBM_FP32_DEV
+        p = P.Params(P.LBM_D2Q9, sc.nx, sc.ny, 1, P.LBM_EOS_VDW, a, B21, 1.0, 0.0, sc.T_reduced, 0.02, 0.8,
+                     precision=prec, check_every=0)
+        rv, rl, _, _ = P.lbm_coexistence(p)
+        p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
+        W = max(4.0, 4.0 * (P.lbm_kappa_for_width(p, 4.0) / 0.02) ** -0.5)
+        cases.append(p)
+        inits.append(L.flat_slab(sc.nx, sc.ny, 1, rl, rv, W, noise=1e-4, seed=3000 + sc.index))
+    nodes = sum(c.N for c in cases)
+    b = P.lbm_batch_create(cases)
+    for i, r in enumerate(inits):
+        P.lbm_batch_init_fields(b, i, r)
+    P.lbm_batch_step(b, 20)                       # autotune + graph capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.lbm_batch_step(b, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    P.lbm_batch_destroy(b)
+    t_seq = 0.0
+    for p, r in zip(cases, inits):
+        with P.Simulation(p) as s:
+            s.init(r).step(10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(steps)
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+    return {"cases": len(cases), "nodes": nodes, "steps": steps, "batched_s": t_batch, "one_by_one_s": t_seq,
+            "speedup": t_seq / t_batch, "batched_MLUPS": nodes * steps / t_batch / 1e6,
+            "one_by_one_MLUPS": nodes * steps / t_seq / 1e6,
+            "fp64_cases": sum(1 for c in cases if c.precision == P.LBM_FP64)}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on a bounded sample of the same workload (48^3, same physics)."""
     from oracle import oracle as O
@@ -130,6 +174,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -178,6 +224,11 @@ def main():
     bytes_lup = 2 * 27 * 4
     achieved = N * bytes_lup / t_k / 1e9
     traffic = traffic_from_profile() if r32["fused"] else None
+    batch = None
+    if not args.no_batch:
+        log("[bench] batched temperature sweep vs one-by-one")
+        batch = batch_sweep(P, torch, args.batch_steps)
+        log(f"[bench] batch {batch['batched_s']:.3f} s vs one-by-one {batch['one_by_one_s']:.3f} s")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -201,6 +252,7 @@ def main():
         "mass_rel_drift_fp32": abs(t32[0] / r32["mass0"] - 1),
         "density_error_fp32_vs_fp64": dens,
         "fp64": fp64,
+        "batch_sweep": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,27 +1,452 @@
-// batch.hip -- batched sweep entry points (persistent kernel; see lbm2p.h).
+// batch.hip -- many independent simulations of uneven sizes in ONE persistent launch.
+//
+// Each case (a full problem statement: lattice, EOS, T/Tc, kappa, tau, precision,
+// grid) is owned by one workgroup, which runs the whole step loop itself:
+//   phase 1: pull-gather every node of the case -> rho, signed psi, g = rho u^3
+//            into the case's field arrays;
+//   workgroup barrier;
+//   phase 2: two-ring Korteweg force from the fields, correction, product-form
+//            equilibria and LBGK (same device functions as the single-case kernels),
+//            written to the other lattice; workgroup barrier; swap.
+// Only workgroup barriers are used: no case waits on another workgroup, so every
+// workgroup finishes after its own step count. The precision branch is uniform per
+// workgroup. One launch of `chunk` steps is captured in a HIP graph at creation;
+// lbm_batch_step replays it. The workgroup size is picked by a small autotuner
+// (timed trial launches) and kept in an in-process cache keyed by the case list.
 #include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
 
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm2p.h"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "runtime_common.hpp"
+#include "step_common.hpp"
 
+using namespace lbm;
+
+namespace {
+
+struct CaseDesc {
+    int D;          // 2 or 3
+    int fp64;       // storage/compute precision
+    Geom g;
+    void *A, *B;    // population lattices (A = current)
+    void *frho, *fpsi, *fg;   // fields in compute precision: rho, s*psi, g[D]
+    const uint8_t *mask;      // nullable
+    double *totals;           // 5 slots: mass, j, domain-error count (FP64)
+    Params<double> pd;
+    Params<float> pf;
+};
+
+// --------------------------------------------------------------- device part
+template <int D, class S, class C>
+__device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, int parity) {
+    constexpr int Q = Lat<D>::Q;
+    const Geom g = cd.g;
+    const uint8_t *mask = cd.mask;
+    C *frho = (C *)cd.frho, *fpsi = (C *)cd.fpsi, *fg = (C *)cd.fg;
+    S *L0 = (S *)cd.A, *L1 = (S *)cd.B;
+    for (int st = 0; st < nsteps; ++st) {
+        const bool even = ((st + parity) & 1) == 0;
+        const S *A = even ? L0 : L1;
+        S *B = even ? L1 : L0;
+        // phase 1: fields of the current state
+        for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
+            const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+            C rho, ga[3] = {C(0), C(0), C(0)};
+            if (mask && mask[n]) {
+                rho = p.rho_w;
+            } else {
+                C h[Q];
+                if (mask)
+                    gather<D, S, C, true>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
+                else
+                    gather<D, S, C, false>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
+                C sum, j[3];
+                moments_of<D, C>(h, sum, j);
+                rho = p.rho_ref + sum;
+                const C rinv = rcp(rho);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const C ua = j[a] * rinv;
+                    ga[a] = rho * ua * ua * ua;
+                }
+            }
+            frho[n] = rho;
+            fpsi[n] = signed_psi(p.eos, rho);
+#pragma unroll
+            for (int a = 0; a < D; ++a) fg[a * g.N + n] = ga[a];
+        }
+        __syncthreads();
+        // phase 2: collide and stream A -> B
+        for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
+            if (mask && mask[n]) continue;
+            const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+            const Nbr<D> nb(g, x, y, z);
+            const C rho = frho[n], spc = fpsi[n];
+            C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
+            static_for<1, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+                constexpr C w3 = C(3.0 * weight<D>(i));
+                const int n1 = nb.at(cx, cy, cz);
+                const int x2 = wrapi(x + 2 * cx, g.nx), y2 = wrapi(y + 2 * cy, g.ny);
+                const int z2 = D == 3 ? wrapi(z + 2 * cz, g.nz) : 0;
+                const int n2 = x2 + g.nx * (y2 + g.ny * z2);
+                const C p1 = fabs(fpsi[n1]), p2 = fabs(fpsi[n2]);
+                const C r1 = frho[n1], r2 = frho[n2];
+                const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
+                const C tc = w3 * (C(2) * r1 - r2);
+                static_for<0, D>([&](auto A_) {
+                    constexpr int a = decltype(A_)::value;
+                    constexpr int ca = Lat<D>::c(i, a);
+                    if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
+                    if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
+                });
+            });
+            C Sf[3] = {C(0), C(0), C(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+            C h[Q];
+            if (mask)
+                gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
+            else
+                gather<D, S, C, false>(A, g.qs, mask, nb, n, h);
+            C drho, j[3];
+            moments_of<D, C>(h, drho, j);
+            const C rinv = rcp(rho);
+            C u[3] = {C(0), C(0), C(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) u[a] = j[a] * rinv;
+            const C omega = omega_of(p, rho);
+            const C cf = (C(1) - C(0.5) * omega) * C(0.5);
+            C Phi[3] = {C(0), C(0), C(0)};
+            Phi[0] = cf * (fg[nb.at(1, 0, 0)] - fg[nb.at(-1, 0, 0)]);
+            Phi[1] = cf * (fg[g.N + nb.at(0, 1, 0)] - fg[g.N + nb.at(0, -1, 0)]);
+            if constexpr (D == 3) Phi[2] = cf * (fg[2 * g.N + nb.at(0, 0, 1)] - fg[2 * g.N + nb.at(0, 0, -1)]);
+            collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                st_at(B + i * g.qs, (unsigned)n, S(h[i]));
+            });
+        }
+        __syncthreads();
+    }
+}
+
+// one kernel per lattice: the register budget of a D2Q9 sweep is not set by the D3Q27 body
+// (D3Q27 cases run with at most 256 threads, which leaves room for the 27-population body)
+template <int D>
+__global__ __launch_bounds__(D == 2 ? 1024 : 256) void k_batch(const CaseDesc *__restrict__ cases, const int *__restrict__ order,
+                                                 int ncases, int nsteps, const int *__restrict__ parity) {
+    const int c = order[blockIdx.x];
+    if (c >= ncases) return;
+    const CaseDesc cd = cases[c];
+    const int par = parity[c];
+    if (cd.fp64) case_steps<D, double, double>(cd, cd.pd, nsteps, par);
+    else case_steps<D, float, float>(cd, cd.pf, nsteps, par);
+}
+
+// flips the per-case lattice parity after a launch of an odd number of steps
+__global__ void k_flip_parity(int *parity, int ncases, int nsteps) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncases) parity[c] = (parity[c] + nsteps) & 1;
+}
+
+thread_local std::string g_batch_err;
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;   // case-list signature -> workgroup size
+
+}  // namespace
+
+// --------------------------------------------------------------- host part
 struct lbm_batch {
+    std::vector<lbm_params> params;
+    std::vector<CaseDesc> host;       // A/B pointers as allocated (parity tracked on the device)
+    std::vector<KernelSet> ks;
+    std::vector<int> nblk;
+    CaseDesc *d_cases = nullptr;
+    int *d_order = nullptr, *d_parity = nullptr;
+    int n2 = 0, n3 = 0;              // cases per lattice; d_order lists the D2Q9 cases first
+    std::vector<void *> allocs;
+    double *partials = nullptr, *d_tot = nullptr, *io = nullptr;
+    size_t io_elems = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int block = 256, chunk = 200;
+    std::vector<int> initialized;
     std::string err;
 };
 
 namespace {
-thread_local std::string g_batch_err;
+
+int bfail(lbm_batch *b, int code, const std::string &m) {
+    if (b) b->err = m; else g_batch_err = m;
+    return code;
 }
 
+#define BHIP(b, call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return bfail((b), LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void free_batch(lbm_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *q : b->allocs) (void)hipFree(q);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int launch(lbm_batch *b, int nsteps, int block) {
+    const int nc = (int)b->host.size();
+    if (b->n2)
+        hipLaunchKernelGGL(k_batch<2>, dim3(b->n2), dim3(block), 0, b->stream, b->d_cases, b->d_order, nc, nsteps,
+                           b->d_parity);
+    if (b->n3)
+        hipLaunchKernelGGL(k_batch<3>, dim3(b->n3), dim3(block < 256 ? block : 256), 0, b->stream, b->d_cases, b->d_order + b->n2, nc,
+                           nsteps, b->d_parity);
+    if (nsteps & 1) hipLaunchKernelGGL(k_flip_parity, dim3((nc + 255) / 256), dim3(256), 0, b->stream, b->d_parity, nc, nsteps);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+// current lattice of case c (host view of the device parity)
+void *current_A(lbm_batch *b, int c, int parity) { return parity ? b->host[c].B : b->host[c].A; }
+
+std::string signature(const lbm_batch *b) {
+    std::string s;
+    for (const auto &cd : b->host)
+        s += std::to_string(cd.D) + ":" + std::to_string(cd.fp64) + ":" + std::to_string(cd.g.N) + ";";
+    return s;
+}
+
+}  // namespace
+
 extern "C" {
-int lbm_batch_create(const lbm_params *, int, lbm_batch **out) {
-    if (out) *out = nullptr;
-    g_batch_err = "batched path not built in this version";
-    return LBM_E_INVAL;
+
+int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
+    if (!out) return bfail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!cases || ncases < 1) return bfail(nullptr, LBM_E_INVAL, "need at least one case");
+    for (int c = 0; c < ncases; ++c) {
+        std::string why;
+        if (!validate_params(&cases[c], &why)) return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": " + why);
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch;
+    if (!b) return bfail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    if (hipStreamCreate(&b->stream) != hipSuccess) { free_batch(b); return bfail(nullptr, LBM_E_HIP, "stream creation failed"); }
+    b->params.assign(cases, cases + ncases);
+    b->host.resize(ncases);
+    b->ks.resize(ncases);
+    b->nblk.resize(ncases);
+    b->initialized.assign(ncases, 0);
+    auto dalloc = [&](size_t bytes) -> void * {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+        b->allocs.push_back(q);
+        return q;
+    };
+    int max_nblk = 0;
+    for (int c = 0; c < ncases; ++c) {
+        const lbm_params &p = cases[c];
+        CaseDesc &cd = b->host[c];
+        cd.D = p.lattice == LBM_D3Q27 ? 3 : 2;
+        cd.fp64 = p.precision == LBM_FP64;
+        cd.g = make_geom(p.nx, p.ny, cd.D == 3 ? p.nz : 1);
+        fill_params(&p, &cd.pd);
+        fill_params(&p, &cd.pf);
+        const size_t s = cd.fp64 ? 8 : 4, N = (size_t)cd.g.N, Q = cd.D == 3 ? 27 : 9;
+        cd.A = dalloc(Q * cd.g.qs * s);
+        cd.B = dalloc(Q * cd.g.qs * s);
+        cd.frho = dalloc(N * s);
+        cd.fpsi = dalloc(N * s);
+        cd.fg = dalloc((size_t)cd.D * N * s);
+        cd.totals = (double *)dalloc(8 * sizeof(double));
+        cd.mask = nullptr;
+        if (!cd.A || !cd.B || !cd.frho || !cd.fpsi || !cd.fg || !cd.totals) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+        if (p.mask) {
+            uint8_t *m = (uint8_t *)dalloc(N);
+            if (!m || hipMemcpy(m, p.mask, N, hipMemcpyHostToDevice) != hipSuccess) { free_batch(b); return bfail(nullptr, LBM_E_HIP, "mask upload failed"); }
+            cd.mask = m;
+        }
+        b->params[c].mask = nullptr;
+        b->ks[c] = kernel_set(cd.D, cd.fp64, cd.mask != nullptr);
+        b->nblk[c] = moment_block_count(cd.D, cd.g);
+        max_nblk = std::max(max_nblk, b->nblk[c]);
+        b->io_elems = std::max(b->io_elems, (size_t)(1 + cd.D) * N);
+    }
+    b->d_cases = (CaseDesc *)dalloc(ncases * sizeof(CaseDesc));
+    b->d_order = (int *)dalloc(ncases * sizeof(int));
+    b->d_parity = (int *)dalloc(ncases * sizeof(int));
+    b->partials = (double *)dalloc((size_t)max_nblk * kPartialSlots * sizeof(double));
+    b->d_tot = (double *)dalloc(8 * sizeof(double));
+    b->io = (double *)dalloc(b->io_elems * sizeof(double));
+    if (!b->d_cases || !b->d_order || !b->d_parity || !b->partials || !b->d_tot || !b->io) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    // largest cases first: they bound the launch, so they are dispatched first
+    std::vector<int> order(ncases);
+    for (int c = 0; c < ncases; ++c) order[c] = c;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        if (b->host[x].D != b->host[y].D) return b->host[x].D < b->host[y].D;   // D2Q9 cases first
+        const double cx = double(b->host[x].g.N) * (b->host[x].fp64 ? 2 : 1);
+        const double cy = double(b->host[y].g.N) * (b->host[y].fp64 ? 2 : 1);
+        return cx > cy;
+    });
+    for (int c = 0; c < ncases; ++c) (b->host[c].D == 2 ? b->n2 : b->n3) += 1;
+    std::vector<int> zero(ncases, 0);
+    if (hipMemcpy(b->d_cases, b->host.data(), ncases * sizeof(CaseDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), ncases * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_parity, zero.data(), ncases * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        free_batch(b);
+        return bfail(nullptr, LBM_E_HIP, "descriptor upload failed");
+    }
+    const char *cs = getenv("LBM2P_BATCH_CHUNK");
+    b->chunk = (cs && atoi(cs) > 0) ? atoi(cs) : 200;
+    *out = b;
+    return LBM_OK;
 }
-int lbm_batch_init_fields(lbm_batch *, int, const double *, const double *) { return LBM_E_INVAL; }
-int lbm_batch_step(lbm_batch *, int64_t) { return LBM_E_INVAL; }
-int lbm_batch_moments(lbm_batch *, int, double *, double *, double *) { return LBM_E_INVAL; }
-void lbm_batch_destroy(lbm_batch *b) { delete b; }
+
+int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const double *u) {
+    if (!b || !rho || icase < 0 || icase >= (int)b->host.size()) return bfail(b, LBM_E_INVAL, "bad argument");
+    CaseDesc &cd = b->host[icase];
+    const size_t N = (size_t)cd.g.N;
+    for (size_t n = 0; n < N; ++n)
+        if (!(rho[n] > 0.0) || !isfinite(rho[n])) return bfail(b, LBM_E_DOMAIN, "initial density must be finite and > 0");
+    int parity = 0;
+    BHIP(b, hipMemcpy(&parity, b->d_parity + icase, sizeof(int), hipMemcpyDeviceToHost));
+    void *A = current_A(b, icase, parity);
+    const void *prm = cd.fp64 ? (const void *)&cd.pd : (const void *)&cd.pf;
+    BHIP(b, hipMemcpyAsync(b->io, rho, N * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    if (u) BHIP(b, hipMemcpyAsync(b->io + N, u, cd.D * N * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    const long long count = (long long)(cd.D == 3 ? 27 : 9) * cd.g.qs;
+    b->ks[icase].fill_zero(b->stream, cd.A, count);
+    b->ks[icase].fill_zero(b->stream, cd.B, count);
+    b->ks[icase].init(b->stream, A, cd.g, cd.mask, prm, cd.frho, b->io, u ? b->io + N : nullptr);
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->initialized[icase] = 1;
+    return LBM_OK;
+}
+
+static int autotune(lbm_batch *b) {
+    const std::string sig = signature(b);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(sig);
+        if (it != g_tune_cache.end()) { b->block = it->second; return LBM_OK; }
+    }
+    const char *env = getenv("LBM2P_BATCH_BLOCK");
+    if (env && atoi(env) > 0) { b->block = atoi(env); return LBM_OK; }
+    // timed trials of a few steps on the live state, then the state is rewound: the trials
+    // run an even number of steps on copies taken and restored through the graph-free path
+    int best = 256;
+    double best_t = 1e30;
+    const int trial_steps = 20;
+    // save every case's current lattice
+    std::vector<std::vector<char>> save(b->host.size());
+    std::vector<int> par(b->host.size());
+    BHIP(b, hipMemcpy(par.data(), b->d_parity, par.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t c = 0; c < b->host.size(); ++c) {
+        const CaseDesc &cd = b->host[c];
+        const size_t bytes = (size_t)(cd.D == 3 ? 27 : 9) * cd.g.qs * (cd.fp64 ? 8 : 4);
+        save[c].resize(bytes);
+        BHIP(b, hipMemcpy(save[c].data(), current_A(b, (int)c, par[c]), bytes, hipMemcpyDeviceToHost));
+    }
+    for (int blk : {256, 512, 1024}) {
+        BHIP(b, hipStreamSynchronize(b->stream));
+        auto t0 = std::chrono::steady_clock::now();
+        if (launch(b, trial_steps, blk)) return bfail(b, LBM_E_HIP, "trial launch failed");
+        BHIP(b, hipStreamSynchronize(b->stream));
+        double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (t < best_t) { best_t = t; best = blk; }
+    }
+    // restore the states (trial steps were even: parity unchanged)
+    for (size_t c = 0; c < b->host.size(); ++c) {
+        const CaseDesc &cd = b->host[c];
+        BHIP(b, hipMemcpy(current_A(b, (int)c, par[c]), save[c].data(), save[c].size(), hipMemcpyHostToDevice));
+    }
+    b->block = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[sig] = best;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t n) {
+    if (!b || n < 0) return bfail(b, LBM_E_INVAL, "bad argument");
+    for (size_t c = 0; c < b->host.size(); ++c)
+        if (!b->initialized[c]) return bfail(b, LBM_E_STATE, "case " + std::to_string(c) + " not initialised");
+    if (n == 0) return LBM_OK;
+    if (!b->exec) {
+        int rc = autotune(b);
+        if (rc) return rc;
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        if (launch(b, b->chunk, b->block)) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(b->stream, &g);
+            return bfail(b, LBM_E_HIP, "capture failed");
+        }
+        BHIP(b, hipStreamEndCapture(b->stream, &b->graph));
+        BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    int64_t left = n;
+    while (left >= b->chunk) {
+        BHIP(b, hipGraphLaunch(b->exec, b->stream));
+        left -= b->chunk;
+    }
+    if (left > 0 && launch(b, (int)left, b->block)) return bfail(b, LBM_E_HIP, "launch failed");
+    BHIP(b, hipStreamSynchronize(b->stream));
+    // FP64 watchdog over every case
+    for (size_t c = 0; c < b->host.size(); ++c) {
+        double t[4];
+        int rc = lbm_batch_moments(b, (int)c, nullptr, nullptr, t);
+        if (rc) return rc;
+        if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) || !isfinite(t[3]))
+            return bfail(b, LBM_E_DIVERGED, "case " + std::to_string(c) + " diverged");
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch *b, int icase, double *rho, double *U, double totals[4]) {
+    if (!b || icase < 0 || icase >= (int)b->host.size()) return bfail(b, LBM_E_INVAL, "bad argument");
+    CaseDesc &cd = b->host[icase];
+    int parity = 0;
+    BHIP(b, hipMemcpy(&parity, b->d_parity + icase, sizeof(int), hipMemcpyDeviceToHost));
+    void *A = current_A(b, icase, parity);
+    const void *prm = cd.fp64 ? (const void *)&cd.pd : (const void *)&cd.pf;
+    const size_t N = (size_t)cd.g.N;
+    // the two-pass moment kernel refreshes rho and g in the case's fields and writes partials
+    b->ks[icase].moments(b->stream, A, cd.g, cd.mask, prm, cd.frho, cd.fg, b->partials);
+    launch_reduce(b->stream, b->partials, b->nblk[icase], b->d_tot);
+    double t[5];
+    BHIP(b, hipMemcpyAsync(t, b->d_tot, 5 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (rho || U) {
+        b->ks[icase].output(b->stream, A, cd.g, cd.mask, prm, cd.frho, cd.fg, b->io, b->io + N);
+        if (rho) BHIP(b, hipMemcpyAsync(rho, b->io, N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        if (U) BHIP(b, hipMemcpyAsync(U, b->io + N, cd.D * N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    }
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipStreamSynchronize(b->stream));
+    if (totals) for (int k = 0; k < 4; ++k) totals[k] = t[k];
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+}
+
 const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
-}
+
+}  // extern "C"

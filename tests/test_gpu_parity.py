@@ -236,3 +236,64 @@ def test_fused_step_matches_two_pass_fp32(dims, masked, monkeypatch):
     assert np.all(np.isfinite(fused[0]))
     assert max_rel(fused[0], two[0]) < 1e-5
     assert np.abs(fused[1] - two[1]).max() < 1e-6
+
+
+# ---------------------------------------------------------------- batched sweep
+def _sweep_cases(n, steps_len_lo=32, steps_len_hi=96):
+    """A reduced temperature sweep: D2Q9 4 x L flat interfaces, FP64 from T/Tc >= 0.95."""
+    sweep = L.temperature_sweep(n, 0.55, 0.99, steps_len_lo, steps_len_hi, 4)
+    fl0 = T.Fluid(T.VDW, 9 / 49, 2 / 21, 0.55)
+    a = 9 / 49 * 0.02 / T.kappa_for_width(fl0, 4.0)
+    out = []
+    for sc in sweep:
+        case = Case(2, sc.nx, sc.ny, a=a, T_reduced=sc.T_reduced)
+        rv, rl = case.coexistence()
+        W = max(4.0, T.interface_width(case.fluid(), 0.02))
+        rho0 = L.flat_slab(sc.nx, sc.ny, 1, rl, rv, W, noise=1e-4, seed=2000 + sc.index)
+        out.append((sc, case, rho0, rv))
+    return out
+
+
+def test_batched_sweep_matches_single_runs_and_oracle():
+    import paper_2112_01975_amd as P
+    cases = _sweep_cases(10)
+    plist = [c.params(1 if not sc.fp64 else 0, rv if not sc.fp64 else 0.0) for sc, c, _, rv in cases]
+    b = P.lbm_batch_create(plist)
+    try:
+        for i, (sc, c, rho0, rv) in enumerate(cases):
+            P.lbm_batch_init_fields(b, i, rho0)
+        P.lbm_batch_step(b, 301)          # odd: exercises the lattice parity flip after the graph chunks
+        for i, (sc, c, rho0, rv) in enumerate(cases):
+            rb, Ub, tb = P.lbm_batch_moments(b, i, c.N, 2)
+            rs, Us, ts = run_gpu(c, rho0, None, 301, precision=1 if not sc.fp64 else 0,
+                                 rho_ref=rv if not sc.fp64 else 0.0)
+            tol = 1e-12 if sc.fp64 else 2e-5
+            assert max_rel(rb, rs) < tol, (i, max_rel(rb, rs))
+            if sc.fp64:
+                ro, Uo, to = run_oracle(c, rho0, None, 301)
+                assert max_rel(rb, ro) < FP64_RHO_TOL
+                assert np.abs(Ub - Uo).max() < FP64_U_TOL
+    finally:
+        P.lbm_batch_destroy(b)
+
+
+def test_batched_mixed_lattices_and_masks():
+    import paper_2112_01975_amd as P
+    c2 = Case(2, 40, 30, a=0.02, T_reduced=0.8, rho_wall=0.9, mask=L.random_mask(40, 30, 1, 0.05, 3))
+    c3 = Case(3, 20, 18, 16, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rv2, rl2 = c2.coexistence()
+    rv3, rl3 = c3.coexistence()
+    r2 = L.drop(40, 30, 1, 8.0, rl2, rv2, 4.0, noise=1e-4, seed=5)
+    r3 = L.drop(20, 18, 16, 5.0, rl3, rv3, 5.0, noise=1e-5, seed=6)
+    b = P.lbm_batch_create([c2.params(0), c3.params(0)])
+    try:
+        P.lbm_batch_init_fields(b, 0, r2)
+        P.lbm_batch_init_fields(b, 1, r3)
+        P.lbm_batch_step(b, 60)
+        for i, (c, r0) in enumerate(((c2, r2), (c3, r3))):
+            rb, Ub, _ = P.lbm_batch_moments(b, i, c.N, c.lattice)
+            ro, Uo, _ = run_oracle(c, r0, None, 60)
+            assert max_rel(rb, ro) < FP64_RHO_TOL
+            assert np.abs(Ub - Uo).max() < FP64_U_TOL
+    finally:
+        P.lbm_batch_destroy(b)
