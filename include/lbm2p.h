@@ -80,9 +80,11 @@ typedef struct lbm_batch lbm_batch;
  * is NULL and the message is available from lbm_last_error(NULL). */
 int lbm_create(const lbm_params *p, lbm_ctx **out);
 
-/* Sets f_i = f_i^eq(rho, u) (eq LBMeq) at every fluid node. rho: host [N],
- * u: host [D][N] or NULL for rest. Records the initial mass and momentum and
- * clears sticky errors. Synchronous. */
+/* Sets f_i = f_i^eq(rho, u) (eq LBMeq) at every fluid node. rho: host [N] (> 0);
+ * u: host [D][N] flow velocity U or NULL for rest. U is the velocity the moments
+ * report (U = u + S/(2 rho), Sec. 2.3.5, Appendix D), so the equilibrium is taken at
+ * the bare velocity u = U - S/(2 rho) with S the source of the given density field;
+ * lbm_moments of the initial state returns (rho, U). Clears sticky errors. Synchronous. */
 int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u);
 
 /* Advances n time steps of eq LBGK (stream-collide with the Korteweg force and
@@ -111,12 +113,20 @@ const char *lbm_last_error(const lbm_ctx *c);
 int lbm_set_stream(lbm_ctx *c, void *hip_stream);
 
 /* Checkpoint: copies the population lattice to / from a host buffer of
- * lbm_population_bytes(c) bytes in storage precision (FP64 f_i or FP32 h_i).
- * The layout is the library's own and opaque; a set of what get returned
+ * lbm_population_bytes(c) bytes in storage precision (FP64 f_i or FP32 h_i), as
+ * Q rows of N values in the order of lbm_velocities; a set of what get returned
  * resumes bit-exactly. Synchronous. */
 int64_t lbm_population_bytes(const lbm_ctx *c);
 int lbm_get_populations(lbm_ctx *c, void *host);
 int lbm_set_populations(lbm_ctx *c, const void *host);
+
+/* Velocity set of the library's population order (eq d3q27vel; D2Q9 drops z): writes
+ * Q triplets (c_x, c_y, c_z) into c (caller-owned, 3*Q ints) and returns Q (9 or 27),
+ * or LBM_E_INVAL. Together with lbm_get_populations this documents the checkpoint
+ * layout: population i of node n is the post-collision value that node n produced,
+ * so the pre-collision f_i(r) is entry i at r - c_i (entry opp(i) at r when r - c_i is
+ * solid); FP32 storage holds f_i - w_i rho_ref. */
+int lbm_velocities(int lattice, int *c);
 
 /* Runs n steps with HIP events around every kernel launch on the context
  * stream and returns the summed device time per kernel kind in ms:

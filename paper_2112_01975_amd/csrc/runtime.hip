@@ -322,6 +322,14 @@ int lbm_set_populations(lbm_ctx *c, const void *host) {
     return watchdog(c);
 }
 
+int lbm_velocities(int lattice, int *c) {
+    if (!c || (lattice != LBM_D2Q9 && lattice != LBM_D3Q27)) return fail(nullptr, LBM_E_INVAL, "bad argument");
+    const int D = lattice == LBM_D3Q27 ? 3 : 2, Q = D == 3 ? 27 : 9;
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) c[3 * i + a] = D == 3 ? Lat<3>::c(i, a) : Lat<2>::c(i, a);
+    return Q;
+}
+
 int lbm_coexistence(const lbm_params *p, double out[4]) {
     if (!p || !out) return fail(nullptr, LBM_E_INVAL, "NULL argument");
     HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);

@@ -24,7 +24,7 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 EXPORTED = [
     "lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments", "lbm_destroy", "lbm_last_error",
     "lbm_set_stream", "lbm_population_bytes", "lbm_get_populations", "lbm_set_populations",
-    "lbm_step_timed", "lbm_coexistence", "lbm_kappa_for_width", "lbm_batch_create",
+    "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
     "lbm_batch_last_error",
 ]
@@ -72,6 +72,7 @@ def lib() -> C.CDLL:
         L.lbm_get_populations.argtypes = [vp, vp]
         L.lbm_set_populations.argtypes = [vp, vp]
         L.lbm_step_timed.argtypes = [vp, i64, vp, vp]
+        L.lbm_velocities.argtypes = [C.c_int, vp]
         L.lbm_coexistence.argtypes = [P, vp]
         L.lbm_kappa_for_width.argtypes = [P, d, C.POINTER(d)]
         L.lbm_batch_create.argtypes = [P, C.c_int, C.POINTER(vp)]
@@ -206,6 +207,14 @@ def lbm_step_timed(ctx, n: int):
     nl = np.zeros(2, dtype=np.int64)
     _check(lib().lbm_step_timed(ctx, int(n), _ptr(ms), _ptr(nl)), ctx)
     return ms, nl
+
+
+def lbm_velocities(lattice: int) -> np.ndarray:
+    c = np.zeros(27 * 3, dtype=np.int32)
+    q = lib().lbm_velocities(lattice, _ptr(c))
+    if q < 0:
+        raise LbmError(q, lbm_last_error(None))
+    return c[: 3 * q].reshape(q, 3)
 
 
 def lbm_coexistence(p: Params):

@@ -86,3 +86,58 @@ def drop_case_inputs(case: Case, radius, width=5.0, noise=1e-5, seed=1003, centr
     rv, rl = case.coexistence()
     rho = L.drop(case.nx, case.ny, case.nz, radius, rl, rv, width, centre=centre, noise=noise, seed=seed)
     return rho, None
+
+
+def oracle_one_step_at_nodes(case: Case, pops_bytes, precision, rho_ref, nodes, radius=6):
+    """One oracle step on (2 radius + 1)^D neighbourhoods of sampled nodes of a GPU state.
+
+    pops_bytes: lbm_get_populations of the GPU state at time t (Q rows of N values in the
+    library's velocity order, post-collision values at the producing node). The physical
+    pre-collision f_i(r) = row i at r - c_i (row opp(i) at r when r - c_i is solid), plus
+    w_i rho_ref for FP32 deviation storage. Each neighbourhood is stepped once by the
+    oracle on a periodic cube; with radius >= 6 the centre's rho and U at t + 1 depend on
+    data inside the cube only. Returns [(rho, U[D])] per node.
+    """
+    import paper_2112_01975_amd as P
+    D, nx, ny, nz, N = case.lattice, case.nx, case.ny, case.nz, case.N
+    cl = P.lbm_velocities(P.LBM_D3Q27 if D == 3 else P.LBM_D2Q9)
+    Q = len(cl)
+    arr = np.frombuffer(pops_bytes, dtype=np.float64 if precision == 0 else np.float32).reshape(Q, N)  # no copy
+    wcl = np.prod(np.where(cl[:, :D] == 0, 2.0 / 3.0, 1.0 / 6.0), axis=1)
+    opp = np.array([int(np.nonzero((cl == -cl[i]).all(axis=1))[0][0]) for i in range(Q)])
+    co, _, _ = O.lattice(D)
+    to_lib = np.array([int(np.nonzero((cl == co[k]).all(axis=1))[0][0]) for k in range(Q)])
+    mask = case.mask
+    m = 2 * radius + 1
+    out = []
+    for (x0, y0, z0) in nodes:
+        ox = (x0 + np.arange(-radius, radius + 1)) % nx
+        oy = (y0 + np.arange(-radius, radius + 1)) % ny
+        oz = (z0 + np.arange(-radius, radius + 1)) % nz if D == 3 else np.array([0])
+        Z, Y, X = np.meshgrid(oz, oy, ox, indexing="ij")
+        idx = (X + nx * (Y + ny * Z)).ravel()
+        f = np.zeros((Q, idx.size))
+        for i in range(Q):
+            sx = (X - cl[i, 0]) % nx
+            sy = (Y - cl[i, 1]) % ny
+            sz = (Z - cl[i, 2]) % nz if D == 3 else Z
+            src = (sx + nx * (sy + ny * sz)).ravel()
+            vals = arr[i, src].astype(np.float64)
+            if mask is not None:
+                sol = mask[src].astype(bool)
+                vals = np.where(sol, arr[opp[i], idx].astype(np.float64), vals)
+            f[i] = vals + wcl[i] * rho_ref
+        cube = Case(D, m, m, m if D == 3 else 1, case.eos, case.a, case.b, case.acentric, case.T_reduced,
+                    case.kappa, case.tau, case.tau_vapour, case.rho_wall,
+                    None if mask is None else mask[idx].copy())
+        cfg = cube.oracle_config()
+        if case.tau_vapour > 0:
+            rv, rl = case.coexistence()
+            cfg.rho_vapour, cfg.rho_liquid = rv, rl
+        o = O.Oracle(cfg, cube.mask)
+        o.set_populations(f[to_lib])
+        o.step(1)
+        r, U, _ = o.moments()
+        cidx = radius + m * (radius + m * (radius if D == 3 else 0))
+        out.append((r[cidx], U[:, cidx]))
+    return out
