@@ -22,6 +22,6 @@ using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, 
                              const void *params, const FusedGrid &);
 
 // nullptr when no fused variant exists for this combination
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool queue);
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty);
 
 }  // namespace lbm

@@ -1,18 +1,20 @@
 // fused_kernels.hip -- single-pass D3Q27 stream-collide step with a z-march (gfx950).
 //
 // One workgroup owns a TX x TY column tile of (x, y) and marches over a chunk of
-// TZ planes in z. For every plane p it pulls the 27 populations of each node of
-// the tile plus a two-node halo ((TX + 4) x (TY + 4) nodes), forms rho, the signed
-// pseudo-potential (eq force_form) and g = rho u^3, and keeps rho / s*psi in a
-// six-plane LDS ring. Two planes later, when planes z-2..z+2 are resident, the
-// tile's plane z is collided: the two-ring Korteweg force (eq Kforce_final) is
-// read from the ring, the diagonal correction (eq correction) from g held in
-// registers (x, y differences) and a four-plane register window (z difference),
-// and the populations are pulled again (the re-read hits L2 / MALL: the same
-// lines were fetched two planes earlier) and written in pull layout to B.
-// Only the populations move through HBM: ~2 Q s bytes per lattice update, with
-// halo and chunk-boundary re-reads served from cache when neighbouring tiles are
-// co-resident (tiles are mapped so that each XCD works on a compact block).
+// TZ planes in z. Each plane p is pulled once: the 27 populations of every tile
+// node, plus rho / g of a two-node halo ((TX + 4) x (TY + 4) nodes), give rho, the
+// signed pseudo-potential (eq force_form) and g = rho u^3; rho and s*psi go into a
+// six-plane LDS ring, g into registers (z difference) and a double-buffered LDS
+// plane (x, y differences). Plane z is collided once planes z-2..z+2 are resident:
+// the two-ring Korteweg force (eq Kforce_final) comes from the ring, the diagonal
+// correction (eq correction) from g, and the populations from a register queue,
+// so every population crosses HBM once in each direction (2 Q s bytes per lattice update plus the chunk's z halo).
+//
+// Software pipeline, one barrier per plane: while plane z is collided, the
+// population registers of plane z are refilled with the pulls of plane z+3 as soon
+// as each collided value is stored, and the halo pulls of plane z+3 are in flight
+// during the stencil. The three queue planes are renamed by unrolling the march by
+// three instead of being moved.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -27,13 +29,55 @@ namespace {
 
 constexpr int NXCD = 8;   // MI355X: 8 XCDs, workgroups dispatched round-robin
 
-template <class S, class C, bool MASK, int FTX, int TY, bool QUEUE>
+// library index of the velocity (cx, cy, cz)
+constexpr int index3(int cx, int cy, int cz) {
+    for (int i = 0; i < 27; ++i)
+        if (Lat<3>::c(i, 0) == cx && Lat<3>::c(i, 1) == cy && Lat<3>::c(i, 2) == cz) return i;
+    return -1;
+}
+
+// Addresses of one node's pull stencil as byte offsets into a population lattice:
+// v[a][b] = offset of the node at (x + a - 1, y + b - 1) in its plane (per lane, fixed
+// for the whole march), zs[l] = offset of plane z + l - 1 (uniform). Population i
+// of node (x, y, z) is pulled from (x, y, z) - c_i at v[1 - cx][1 - cy] + zs[1 - cz] +
+// i * qs * sizeof(S); the uniform part goes into the scalar offset of the load.
+struct Stencil {
+    unsigned v[3][3];
+};
+
+template <int i, class S, class C, bool MASK>
+__device__ __forceinline__ C pull(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Stencil &st,
+                                  const unsigned (&zs)[3]) {
+    constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+    const unsigned vo = st.v[1 - cx][1 - cy];
+    if constexpr (MASK && i != 0) {
+        // halfway bounce-back: from a solid source node take the opposite population
+        // that this node produced itself
+        const bool solid = ld_at(mask, (vo + zs[1 - cz]) / (unsigned)sizeof(S));
+        const unsigned off = solid ? st.v[1][1] + zs[1] + (unsigned)opp<3>(i) * A.qsb : vo + zs[1 - cz] + (unsigned)i * A.qsb;
+        return C(A.load_at(off, 0u));
+    } else {
+        return C(A.load_at(vo, zs[1 - cz] + (unsigned)i * A.qsb));
+    }
+}
+
+template <class S, class C, bool MASK>
+__device__ __forceinline__ void pull_all(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Stencil &st,
+                                         const unsigned (&zs)[3], C (&h)[27]) {
+    static_for<0, 27>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        h[i] = pull<i, S, C, MASK>(A, mask, st, zs);
+    });
+}
+
+template <class S, class C, bool MASK, int FTX, int TY>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                       const uint8_t *__restrict__ mask, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
     constexpr int HX = FTX + 4, HY = TY + 4, HP = HX * HY;
     constexpr int NHALO = HP - FTX * TY;
     constexpr int RING = 6;
+    constexpr unsigned SB = sizeof(S);
     __shared__ C s_rho[RING * HP];
     __shared__ C s_psi[RING * HP];
     __shared__ C s_gxy[2][2][HP];
@@ -49,180 +93,237 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     const int x0 = tix * FTX, y0 = tiy * TY, z0 = zc * fg.tz;
 
     const PopBuf<S> Ab(A, g.qs, fg.pop_bytes), Bb(B, g.qs, fg.pop_bytes);
+    // a zero-extent view of A: loads through it return 0 without touching memory
+    const PopBuf<S> Anull(A, g.qs, 0u);
     const int t = threadIdx.x;
     const int tx = t & (FTX - 1), ty = t / FTX;
     const int e_int = (ty + 2) * HX + tx + 2;
     const bool own = (x0 + tx < g.nx) && (y0 + ty < g.ny);
     const int nxy = g.nx * g.ny;
-    // loop-invariant neighbour coordinates of this thread's interior node
-    int ixs[3], iry[3];
-    {
-        const int gx = wrapi(x0 + tx, g.nx), gy = wrapi(y0 + ty, g.ny);
-        ixs[0] = wrapi(gx - 1, g.nx); ixs[1] = gx; ixs[2] = wrapi(gx + 1, g.nx);
-        iry[0] = g.nx * wrapi(gy - 1, g.ny); iry[1] = g.nx * gy; iry[2] = g.nx * wrapi(gy + 1, g.ny);
-    }
-    // ... and of the (at most one) halo node it fills: rows 0, 1, TY+2, TY+3, then
-    // columns 0, 1, HX-2, HX-1 of the staged plane
+    auto stencil_of = [&](int x, int y, Stencil &st) __attribute__((always_inline)) {
+        const int gx = wrapi(x, g.nx), gy = wrapi(y, g.ny);
+        const int xs[3] = {wrapi(gx - 1, g.nx), gx, wrapi(gx + 1, g.nx)};
+        const int ry[3] = {g.nx * wrapi(gy - 1, g.ny), g.nx * gy, g.nx * wrapi(gy + 1, g.ny)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st.v[a][c] = (unsigned)(xs[a] + ry[c]) * SB;
+    };
+    // this thread's tile node and the (at most one) halo node it stages: rows 0, 1,
+    // TY+2, TY+3, then columns 0, 1, HX-2, HX-1 of the staged plane
+    Stencil si, sh;
+    stencil_of(x0 + tx, y0 + ty, si);
     static_assert(NHALO <= NT, "one halo node per thread at most");
     const bool has_halo = t < NHALO;
-    int e_halo = 0, hxs[3] = {0, 0, 0}, hry[3] = {0, 0, 0};
-    if (has_halo) {
-        int lx, ly;
+    int e_halo = 0;
+    {
+        int lx = 0, ly = 0;
         if (t < 4 * HX) {
             const int r = t / HX;
             lx = t % HX;
             ly = r < 2 ? r : TY + r;
-        } else {
+        } else if (has_halo) {
             const int q = t - 4 * HX, c4 = q % 4;
             ly = 2 + q / 4;
             lx = c4 < 2 ? c4 : FTX + c4;
         }
         e_halo = ly * HX + lx;
-        const int hx = wrapi(x0 - 2 + lx, g.nx), hy = wrapi(y0 - 2 + ly, g.ny);
-        hxs[0] = wrapi(hx - 1, g.nx); hxs[1] = hx; hxs[2] = wrapi(hx + 1, g.nx);
-        hry[0] = g.nx * wrapi(hy - 1, g.ny); hry[1] = g.nx * hy; hry[2] = g.nx * wrapi(hy + 1, g.ny);
+        stencil_of(x0 - 2 + lx, y0 - 2 + ly, sh);
     }
 
     // register windows: gz of planes z-1..z+2, dgx/dgy of planes z..z+2
     C gz_m1 = C(0), gz_0 = C(0), gz_p1 = C(0), gz_p2 = C(0);
     C dgx_0 = C(0), dgx_p1 = C(0), dgx_p2 = C(0);
     C dgy_0 = C(0), dgy_p1 = C(0), dgy_p2 = C(0);
-    // QUEUE: the populations this thread pulled for planes z, z+1, z+2 stay in registers
-    // until plane z is collided (no second pull); otherwise they are pulled again.
+    // populations this thread pulled for planes z, z+1, z+2 and their (sum h, j)
     C q0[27], q1[27], q2[27];
-    C m0[4], m1[4], m2[4];   // QUEUE: (sum h, j) of the queued planes
+    C m0[4], m1[4], m2[4];
 
-#pragma unroll 1
-    for (int k = -4; k < fg.tz; ++k) {
-        // ---------------- gather plane pz = z0 + k + 2 into ring slot (k + 4) % 6
-        const int pz = wrapi(z0 + k + 2, g.nz);
-        const int pl[3] = {nxy * wrapi(pz - 1, g.nz), nxy * pz, nxy * wrapi(pz + 1, g.nz)};
-        const int slot = ((k + 4) % RING) * HP;
-        const int buf = (k + 4) & 1;
-        {
-            C rho, ga[3] = {C(0), C(0), C(0)};
-            const int n = ixs[1] + iry[1] + pl[1];
-            if (MASK && mask[n]) {
-                rho = p.rho_w;
-            } else {
-                C (&h)[27] = q2;
-                gather_buf<3, S, C, MASK>(Ab, mask, Nbr<3>(ixs, iry, pl), n, h);
-                C sum, j[3];
-                moments_of<3, C>(h, sum, j);
-                m2[0] = sum; m2[1] = j[0]; m2[2] = j[1]; m2[3] = j[2];
-                rho = p.rho_ref + sum;
-                const C rinv = rcp(rho);
+    // byte offsets of planes pz-1, pz, pz+1 (any integer pz)
+    auto planes = [&](int pz, unsigned (&zs)[3]) __attribute__((always_inline)) {
+        zs[0] = (unsigned)(nxy * wrapi(pz - 1, g.nz)) * SB;
+        zs[1] = (unsigned)(nxy * wrapi(pz, g.nz)) * SB;
+        zs[2] = (unsigned)(nxy * wrapi(pz + 1, g.nz)) * SB;
+    };
+    auto solid_at = [&](const Stencil &st, const unsigned (&zs)[3]) __attribute__((always_inline)) {
+        return MASK && mask[(st.v[1][1] + zs[1]) / SB];
+    };
+    // rho, s*psi and g_x, g_y of one staged node into ring slot `slot` / g buffer `buf`;
+    // returns g_z. h holds the node's pulled populations, m receives (sum h, j).
+    auto stage = [&](int e, bool solid, const C (&h)[27], C (&m)[4], int slot, int buf) __attribute__((always_inline)) {
+        C rho, ga[3] = {C(0), C(0), C(0)};
+        if (MASK && solid) {
+            rho = p.rho_w;
+        } else {
+            C sum, j[3];
+            moments_of<3, C>(h, sum, j);
+            m[0] = sum; m[1] = j[0]; m[2] = j[1]; m[3] = j[2];
+            rho = p.rho_ref + sum;
+            const C rinv = rcp(rho);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const C ua = j[a] * rinv;
-                    ga[a] = rho * ua * ua * ua;
-                }
-            }
-            s_rho[slot + e_int] = rho;
-            s_psi[slot + e_int] = signed_psi(p.eos, rho);
-            s_gxy[buf][0][e_int] = ga[0];
-            s_gxy[buf][1][e_int] = ga[1];
-            gz_p2 = ga[2];
-        }
-        if (has_halo) {
-            C rho, ga[2] = {C(0), C(0)};
-            const int n = hxs[1] + hry[1] + pl[1];
-            if (MASK && mask[n]) {
-                rho = p.rho_w;
-            } else {
-                C h[27];
-                gather_buf<3, S, C, MASK>(Ab, mask, Nbr<3>(hxs, hry, pl), n, h);
-                C sum, j[3];
-                moments_of<3, C>(h, sum, j);
-                rho = p.rho_ref + sum;
-                const C rinv = rcp(rho);
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const C ua = j[a] * rinv;
-                    ga[a] = rho * ua * ua * ua;
-                }
-            }
-            s_rho[slot + e_halo] = rho;
-            s_psi[slot + e_halo] = signed_psi(p.eos, rho);
-            s_gxy[buf][0][e_halo] = ga[0];
-            s_gxy[buf][1][e_halo] = ga[1];
-        }
-        __syncthreads();
-        dgx_p2 = s_gxy[buf][0][e_int + 1] - s_gxy[buf][0][e_int - 1];
-        dgy_p2 = s_gxy[buf][1][e_int + HX] - s_gxy[buf][1][e_int - HX];
-
-        // ---------------- collide plane z = z0 + k
-        const int z = z0 + k;
-        if (k >= 0 && own && z < g.nz) {
-            const int zpl[3] = {nxy * wrapi(z - 1, g.nz), nxy * z, nxy * wrapi(z + 1, g.nz)};
-            const int n = ixs[1] + iry[1] + zpl[1];
-            if (!(MASK && mask[n])) {
-                const int sb = (k + 2) % RING;   // ring slot of plane z
-                const int base[5] = {((sb + 4) % RING) * HP, ((sb + 5) % RING) * HP, sb * HP,
-                                     ((sb + 1) % RING) * HP, ((sb + 2) % RING) * HP};   // planes z-2..z+2
-                const C rho = s_rho[base[2] + e_int], spc = s_psi[base[2] + e_int];
-                C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
-                static_for<1, 27>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
-                    constexpr int o1 = cy * HX + cx;
-                    constexpr C w3 = C(3.0 * weight<3>(i));
-                    const int q1 = base[2 + cz] + e_int + o1, q2 = base[2 + 2 * cz] + e_int + 2 * o1;
-                    const C p1 = fabs(s_psi[q1]), p2 = fabs(s_psi[q2]);
-                    const C r1 = s_rho[q1], r2 = s_rho[q2];
-                    const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
-                    const C tc = w3 * (C(2) * r1 - r2);
-                    static_for<0, 3>([&](auto A_) {
-                        constexpr int a = decltype(A_)::value;
-                        constexpr int ca = Lat<3>::c(i, a);
-                        if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
-                        if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
-                    });
-                });
-                C Sf[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
-                C h[27];
-                C drho, j[3];
-                if constexpr (QUEUE) {
-#pragma unroll
-                    for (int i = 0; i < 27; ++i) h[i] = q0[i];
-                    drho = m0[0]; j[0] = m0[1]; j[1] = m0[2]; j[2] = m0[3];
-                } else {
-                    gather_buf<3, S, C, MASK>(Ab, mask, Nbr<3>(ixs, iry, zpl), n, h);
-                    moments_of<3, C>(h, drho, j);
-                }
-                const C rinv = rcp(rho);
-                C u[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) u[a] = j[a] * rinv;
-                const C omega = omega_of(p, rho);
-                const C cf = (C(1) - C(0.5) * omega) * C(0.5);
-                const C Phi[3] = {cf * dgx_0, cf * dgy_0, cf * (gz_p1 - gz_m1)};
-                collide<3, C>(h, rho, drho, u, Sf, Phi, omega);
-                static_for<0, 27>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    Bb.store(i, (unsigned)n, S(h[i]));
-                });
+            for (int a = 0; a < 3; ++a) {
+                const C ua = j[a] * rinv;
+                ga[a] = rho * ua * ua * ua;
             }
         }
-        // ---------------- shift the register windows by one plane
-        gz_m1 = gz_0; gz_0 = gz_p1; gz_p1 = gz_p2;
+        s_rho[slot + e] = rho;
+        s_psi[slot + e] = signed_psi(p.eos, rho);
+        s_gxy[buf][0][e] = ga[0];
+        s_gxy[buf][1][e] = ga[1];
+        return ga[2];
+    };
+    // after the barrier that publishes a plane: shift the windows, x / y differences of g
+    auto shift_windows = [&](C gz_new, int buf) __attribute__((always_inline)) {
+        gz_m1 = gz_0; gz_0 = gz_p1; gz_p1 = gz_p2; gz_p2 = gz_new;
         dgx_0 = dgx_p1; dgx_p1 = dgx_p2;
         dgy_0 = dgy_p1; dgy_p1 = dgy_p2;
-        if constexpr (QUEUE) {
-#pragma unroll
-            for (int i = 0; i < 27; ++i) { q0[i] = q1[i]; q1[i] = q2[i]; }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { m0[i] = m1[i]; m1[i] = m2[i]; }
+        dgx_p2 = s_gxy[buf][0][e_int + 1] - s_gxy[buf][0][e_int - 1];
+        dgy_p2 = s_gxy[buf][1][e_int + HX] - s_gxy[buf][1][e_int - HX];
+    };
+    // whole plane z0 + j (prologue, j = -2..2): pull into h, stage, publish
+    auto prologue_plane = [&](int j, C (&h)[27], C (&m)[4]) __attribute__((always_inline)) {
+        unsigned zs[3];
+        planes(z0 + j, zs);
+        const int slot = ((j + 2) % RING) * HP, buf = (j + 2) & 1;
+        const bool solid = solid_at(si, zs);
+        if (!solid) pull_all<S, C, MASK>(Ab, mask, si, zs, h);
+        const C gzn = stage(e_int, solid, h, m, slot, buf);
+        if (has_halo) {
+            C hh[27], mh[4];
+            const bool hs = solid_at(sh, zs);
+            if (!hs) pull_all<S, C, MASK>(Ab, mask, sh, zs, hh);
+            stage(e_halo, hs, hh, mh, slot, buf);
         }
+        __syncthreads();
+        shift_windows(gzn, buf);
+    };
+
+    // one plane of the march (k = 0 .. tz-1, z = z0 + k): collide plane z from (qa, ma),
+    // refill qa with the pulls of plane z+3 as the collided values leave, stage plane z+3
+    auto march = [&](int k, C (&qa)[27], C (&ma)[4]) __attribute__((always_inline)) {
+        const int z = z0 + k;
+        unsigned zs3[3];
+        planes(z + 3, zs3);
+        const int slot = ((k + 5) % RING) * HP, buf = (k + 5) & 1;
+        const bool need3 = k + 1 < fg.tz;   // plane z+3 feeds the stencil of z+1
+        const bool halo = has_halo && need3;
+        C hh[27];
+        if (halo && !solid_at(sh, zs3)) pull_all<S, C, MASK>(Ab, mask, sh, zs3, hh);
+
+        const unsigned zoff = (unsigned)(nxy * (z < g.nz ? z : 0)) * SB;
+        const bool act = own && z < g.nz && !(MASK && mask[(si.v[1][1] + zoff) / SB]);
+        C Sf[3] = {C(0), C(0), C(0)};
+        C rho = C(1);
+        if (act) {
+            const int base[5] = {(k % RING) * HP, ((k + 1) % RING) * HP, ((k + 2) % RING) * HP,
+                                 ((k + 3) % RING) * HP, ((k + 4) % RING) * HP};   // planes z-2..z+2
+            rho = s_rho[base[2] + e_int];
+            const C spc = s_psi[base[2] + e_int];
+            C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
+            static_for<1, 27>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+                constexpr int o1 = cy * HX + cx;
+                constexpr C w3 = C(3.0 * weight<3>(i));
+                const int r1 = base[2 + cz] + e_int + o1, r2 = base[2 + 2 * cz] + e_int + 2 * o1;
+                const C tp = w3 * (C(4.0 / 3.0) * fabs(s_psi[r1]) - C(1.0 / 6.0) * fabs(s_psi[r2]));
+                const C tc = w3 * (C(2) * s_rho[r1] - s_rho[r2]);
+                static_for<0, 3>([&](auto A_) {
+                    constexpr int a = decltype(A_)::value;
+                    constexpr int ca = Lat<3>::c(i, a);
+                    if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
+                    if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
+                });
+            });
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+        }
+        if (halo) {
+            C mh[4];
+            stage(e_halo, solid_at(sh, zs3), hh, mh, slot, buf);
+        }
+
+        // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
+        // loads go to Anull
+        const PopBuf<S> src = need3 ? Ab : Anull;
+        if (act) {
+            constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
+            const C drho = ma[0];
+            const C rinv = rcp(rho);
+            const C omega = omega_of(p, rho);
+            const C cf = (C(1) - C(0.5) * omega) * C(0.5);
+            const C Phi[3] = {cf * dgx_0, cf * dgy_0, cf * (gz_p1 - gz_m1)};
+            // per-axis triplets of the deviation-form equilibria (see collide())
+            C dv[3][3], Av[3][3], Dv[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const C ua = ma[1 + a] * rinv, u2 = ua * ua;
+                dv[a][0] = C(0.5) * (u2 - ua);
+                dv[a][1] = -u2;
+                dv[a][2] = C(0.5) * (u2 + ua);
+                const C s = Sf[a] * rinv;
+                const C de = s * (C(2) * ua + s) + Phi[a] * rinv;
+                Dv[a][0] = C(0.5) * (de - s);
+                Dv[a][1] = -de;
+                Dv[a][2] = C(0.5) * (de + s);
+                Av[a][0] = W0 + dv[a][0]; Av[a][1] = W1 + dv[a][1]; Av[a][2] = W0 + dv[a][2];
+            }
+            const C om1 = C(1) - omega, omd = omega * drho;
+            C rem = drho;
+            // (c_x, c_y) pairs outermost so that only one pair's x-y factors are live
+            static_for<0, 9>([&](auto P_) {
+                constexpr int kx = decltype(P_)::value / 3, ky = decltype(P_)::value % 3;
+                constexpr C Wx = kx == 1 ? W1 : W0;
+                constexpr C WW = (kx == 1 ? W1 : W0) * (ky == 1 ? W1 : W0);
+                const C E = dv[0][kx] * Av[1][ky] + Wx * dv[1][ky];
+                const C F = Dv[0][kx] * (Av[1][ky] + Dv[1][ky]) + Av[0][kx] * Dv[1][ky];
+                const C AA = Av[0][kx] * Av[1][ky];
+                static_for<0, 3>([&](auto Z_) {
+                    constexpr int kz = decltype(Z_)::value;
+                    constexpr int i = index3(kx - 1, ky - 1, kz - 1);
+                    if constexpr (i != 0) {
+                        constexpr C wi = C(weight<3>(i));
+                        const C eqd = Av[2][kz] * E + WW * dv[2][kz];
+                        const C fsd = (Av[2][kz] + Dv[2][kz]) * F + AA * Dv[2][kz];
+                        const C hn = om1 * qa[i] + omd * wi + rho * (omega * eqd + fsd);
+                        rem -= hn;
+                        Bb.store_at(si.v[1][1], zoff + (unsigned)i * Bb.qsb, S(hn));
+                        qa[i] = pull<i, S, C, MASK>(src, mask, si, zs3);
+                        // keep the refill load here: left to itself the scheduler sinks all
+                        // loads below the last store, and nothing overlaps their latency
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                });
+            });
+            // rest population as the remainder: the per-node mass error stays an unbiased rounding
+            Bb.store_at(si.v[1][1], zoff, S(rem));
+            qa[0] = pull<0, S, C, MASK>(src, mask, si, zs3);
+        } else {
+            pull_all<S, C, MASK>(src, mask, si, zs3, qa);
+        }
+        C gzn = C(0);
+        if (need3) gzn = stage(e_int, solid_at(si, zs3), qa, ma, slot, buf);
+        __syncthreads();
+        shift_windows(gzn, buf);
+    };
+
+    prologue_plane(-2, q0, m0);
+    prologue_plane(-1, q0, m0);
+    prologue_plane(0, q0, m0);
+    prologue_plane(1, q1, m1);
+    prologue_plane(2, q2, m2);
+#pragma unroll 1
+    for (int k = 0; k < fg.tz; k += 3) {
+        march(k, q0, m0);
+        if (k + 1 < fg.tz) march(k + 1, q1, m1);
+        if (k + 2 < fg.tz) march(k + 2, q2, m2);
     }
 }
 
-template <class S, class C, bool MASK, int TX, int TY, bool QUEUE>
+template <class S, class C, bool MASK, int TX, int TY>
 void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm,
                   const FusedGrid &fg) {
-    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, QUEUE>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
+    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
                        mask, *(const Params<C> *)prm, fg);
 }
 
@@ -243,22 +344,16 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
 }
 
 namespace {
-template <int TX, int TY, bool QUEUE> FusedLaunch pick(bool masked) {
-    return masked ? launch_fused<float, float, true, TX, TY, QUEUE> : launch_fused<float, float, false, TX, TY, QUEUE>;
+template <int TX, int TY> FusedLaunch pick(bool masked) {
+    return masked ? launch_fused<float, float, true, TX, TY> : launch_fused<float, float, false, TX, TY>;
 }
 }  // namespace
 
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool queue) {
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty) {
     if (fp64) return nullptr;
-    if (queue) {
-        if (tx == 64 && ty == 8) return pick<64, 8, true>(masked);
-        if (tx == 32 && ty == 8) return pick<32, 8, true>(masked);
-        if (tx == 32 && ty == 16) return pick<32, 16, true>(masked);
-        return nullptr;
-    }
-    if (tx == 64 && ty == 8) return pick<64, 8, false>(masked);
-    if (tx == 32 && ty == 8) return pick<32, 8, false>(masked);
-    if (tx == 32 && ty == 16) return pick<32, 16, false>(masked);
+    if (tx == 64 && ty == 8) return pick<64, 8>(masked);
+    if (tx == 32 && ty == 8) return pick<32, 8>(masked);
+    if (tx == 32 && ty == 16) return pick<32, 16>(masked);
     return nullptr;
 }
 

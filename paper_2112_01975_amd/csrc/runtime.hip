@@ -140,7 +140,7 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         const int tz = env_int("LBM2P_FUSED_TZ", 128);
         const unsigned long long bytes = (unsigned long long)c->Q * (unsigned long long)c->g.qs * c->sbytes;
         if (bytes < 0xFFFFFFFFull) {   // one buffer resource addresses the whole lattice
-            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, env_int("LBM2P_FUSED_QUEUE", 1) != 0);
+            c->fused = fused_launcher(c->fp64, c->masked, tx, ty);
             if (c->fused) {
                 c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
                 c->fg.pop_bytes = (unsigned)bytes;

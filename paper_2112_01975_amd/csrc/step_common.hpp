@@ -101,12 +101,28 @@ template <class S> struct PopBuf {
           qsb((unsigned)(qs * (long long)sizeof(S))) {}
     __device__ __forceinline__ S load(int i, unsigned node) const;
     __device__ __forceinline__ void store(int i, unsigned node, S v) const;
+    // explicit byte offsets: voff per lane, soff uniform
+    __device__ __forceinline__ S load_at(unsigned voff, unsigned soff) const;
+    __device__ __forceinline__ void store_at(unsigned voff, unsigned soff, S v) const;
 };
 template <> __device__ __forceinline__ float PopBuf<float>::load(int i, unsigned node) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, node * 4u, (unsigned)i * qsb, 0));
 }
 template <> __device__ __forceinline__ void PopBuf<float>::store(int i, unsigned node, float v) const {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, node * 4u, (unsigned)i * qsb, 0);
+}
+template <> __device__ __forceinline__ float PopBuf<float>::load_at(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ void PopBuf<float>::store_at(unsigned voff, unsigned soff, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ double PopBuf<double>::load_at(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ void PopBuf<double>::store_at(unsigned voff, unsigned soff, double v) const {
+    using u2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
 template <> __device__ __forceinline__ double PopBuf<double>::load(int i, unsigned node) const {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, node * 8u, (unsigned)i * qsb, 0));
