@@ -143,6 +143,66 @@ def batch_sweep(P, torch, steps):
             "fp64_cases": sum(1 for c in cases if c.precision == P.LBM_FP64)}
 
 
+def timed_mlups(P, torch, p, rho0, U0, steps, warmup):
+    """MLUPS of lbm_step on one workload (state resident in HBM, synchronised both sides)."""
+    with P.Simulation(p) as sim:
+        sim.init(rho0, U0)
+        P.lbm_set_stream(sim.ctx, torch.cuda.current_stream().cuda_stream)
+        P.lbm_step(sim.ctx, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.lbm_step(sim.ctx, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, _, tot = sim.moments(want_fields=False)
+    return p.N * steps / dt / 1e6, bool(np.isfinite(tot).all())
+
+
+def other_workloads(P, torch):
+    """The other full-size workloads of the path, MLUPS in both storage precisions:
+    - D2Q9 512^2 static drop R = 60 (van der Waals T/Tc = 0.8, kappa 0.02, a for W = 4,
+      tau 0.8): the whole lattice fits in the MALL, so only MLUPS are meaningful;
+    - D3Q27 512 x 256 x 256 drop impact on a textured wall (floor plus 8 x 8 pillars of
+      height 16 every 16 nodes; Peng-Robinson T/Tc = 0.6, a for W = 5, kappa 0.02;
+      nu_vapour = 15 nu_liquid with tau_liquid = 0.55; wall density = vapour density;
+      drop R = 40 at (256, 128, 77) moving at -0.05 along z): MLUPS over all nodes and
+      MFLUPS over fluid nodes."""
+    import lbm_inputs as L
+    out = {}
+    base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.8, 0.02, 0.8)
+    a2 = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
+    d2 = {}
+    for prec, name in ((P.LBM_FP32_DEV, "fp32"), (P.LBM_FP64, "fp64")):
+        p = P.Params(P.LBM_D2Q9, 512, 512, 1, P.LBM_EOS_VDW, a2, B21, 1.0, 0.0, 0.8, 0.02, 0.8, precision=prec,
+                     check_every=-1)
+        rv, rl, _, _ = P.lbm_coexistence(p)
+        p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
+        rho0 = L.drop(512, 512, 1, 60.0, rl, rv, 4.0, noise=1e-4, seed=1003)
+        d2[name], ok = timed_mlups(P, torch, p, rho0, None, 1000, 50)
+        d2[name + "_finite"] = ok
+    out["d2q9_512x512_drop"] = {"unit": "MLUPS", "steps": 1000, **d2}
+    nx, ny, nz = 512, 256, 256
+    base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
+    a3 = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)
+    mask = L.pillar_mask(nx, ny, nz, 8, 8, 16)
+    fluid = int((mask == 0).sum())
+    d3 = {}
+    for prec, name in ((P.LBM_FP32_DEV, "fp32"), (P.LBM_FP64, "fp64")):
+        p = P.Params(P.LBM_D3Q27, nx, ny, nz, P.LBM_EOS_PR, a3, B21, 1.0, 0.344, 0.6, 0.02, 0.55,
+                     tau_vapour=0.5 + 15 * 0.05, mask=mask, precision=prec, check_every=-1)
+        rv, rl, _, _ = P.lbm_coexistence(p)
+        p.rho_liquid, p.rho_vapour, p.rho_wall = rl, rv, rv
+        p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
+        if name == "fp32":
+            rho0 = L.drop(nx, ny, nz, 40.0, rl, rv, 5.0, centre=(256.0, 128.0, 77.0), noise=1e-5, seed=1005)
+            rho0 = np.where(mask.astype(bool), rv, rho0)
+            U0 = L.impact_drop_velocity(rho0, rl, rv, 3, -0.05, 2)
+        mlups, ok = timed_mlups(P, torch, p, rho0, U0, 50, 5)
+        d3[name] = {"MLUPS": mlups, "MFLUPS": mlups * fluid / p.N, "finite": ok}
+    out["d3q27_512x256x256_impact"] = {"steps": 50, "fluid_nodes": fluid, "nodes": nx * ny * nz, **d3}
+    return out
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on a bounded sample of the same workload (48^3, same physics)."""
     from oracle import oracle as O
@@ -176,6 +236,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2 and drop-impact legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -229,6 +290,11 @@ def main():
         log("[bench] batched temperature sweep vs one-by-one")
         batch = batch_sweep(P, torch, args.batch_steps)
         log(f"[bench] batch {batch['batched_s']:.3f} s vs one-by-one {batch['one_by_one_s']:.3f} s")
+    other = None
+    if not args.no_other:
+        log("[bench] other workloads (D2Q9 512^2, D3Q27 512x256x256 impact)")
+        other = other_workloads(P, torch)
+        log(f"[bench] other {json.dumps(other)}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -253,6 +319,7 @@ def main():
         "density_error_fp32_vs_fp64": dens,
         "fp64": fp64,
         "batch_sweep": batch,
+        "other_workloads": other,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
