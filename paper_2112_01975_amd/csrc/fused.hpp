@@ -18,8 +18,19 @@ struct FusedGrid {
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz);
 
-using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, const uint8_t *mask,
+// Solid geometry for the fused step (both nullptr without solid nodes):
+//   links[n]  per-node solid-neighbour bits from fused_links;
+//   pflags[z] bit 0: plane z has a solid node, bit 1: planes z-1..z+1 have one.
+struct FusedMask {
+    const uint32_t *links;
+    const uint32_t *pflags;
+};
+
+using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, const FusedMask &,
                              const void *params, const FusedGrid &);
+
+// bit i of links[n]: the source node n - c_i of population i is solid; bit 27: n is solid
+void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g);
 
 // nullptr when no fused variant exists for this combination
 FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty);

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "fused.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
@@ -45,15 +47,18 @@ struct Stencil {
     unsigned v[3][3];
 };
 
+// Solid-neighbour bits of a node (built once per geometry by k_links): bit i is set
+// when the source node r - c_i of population i is solid, bit LINK_SELF when r is.
+constexpr int LINK_SELF = 27;
+
 template <int i, class S, class C, bool MASK>
-__device__ __forceinline__ C pull(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Stencil &st,
-                                  const unsigned (&zs)[3]) {
+__device__ __forceinline__ C pull(const PopBuf<S> &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3]) {
     constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
     const unsigned vo = st.v[1 - cx][1 - cy];
     if constexpr (MASK && i != 0) {
         // halfway bounce-back: from a solid source node take the opposite population
         // that this node produced itself
-        const bool solid = ld_at(mask, (vo + zs[1 - cz]) / (unsigned)sizeof(S));
+        const bool solid = (lm >> i) & 1u;
         const unsigned off = solid ? st.v[1][1] + zs[1] + (unsigned)opp<3>(i) * A.qsb : vo + zs[1 - cz] + (unsigned)i * A.qsb;
         return C(A.load_at(off, 0u));
     } else {
@@ -62,17 +67,17 @@ __device__ __forceinline__ C pull(const PopBuf<S> &A, const uint8_t *__restrict_
 }
 
 template <class S, class C, bool MASK>
-__device__ __forceinline__ void pull_all(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Stencil &st,
-                                         const unsigned (&zs)[3], C (&h)[27]) {
+__device__ __forceinline__ void pull_all(const PopBuf<S> &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3],
+                                         C (&h)[27]) {
     static_for<0, 27>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        h[i] = pull<i, S, C, MASK>(A, mask, st, zs);
+        h[i] = pull<i, S, C, MASK>(A, lm, st, zs);
     });
 }
 
 template <class S, class C, bool MASK, int FTX, int TY>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
-                                                      const uint8_t *__restrict__ mask, Params<C> p, FusedGrid fg) {
+                                                      FusedMask fm, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
     constexpr int HX = FTX + 4, HY = TY + 4, HP = HX * HY;
     constexpr int NHALO = HP - FTX * TY;
@@ -145,8 +150,14 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         zs[1] = (unsigned)(nxy * wrapi(pz, g.nz)) * SB;
         zs[2] = (unsigned)(nxy * wrapi(pz + 1, g.nz)) * SB;
     };
-    auto solid_at = [&](const Stencil &st, const unsigned (&zs)[3]) __attribute__((always_inline)) {
-        return MASK && mask[(st.v[1][1] + zs[1]) / SB];
+    // solid-neighbour bits of the node of stencil st in plane zs[1]
+    auto links_at = [&](const Stencil &st, const unsigned (&zs)[3]) __attribute__((always_inline)) {
+        return fm.links[(st.v[1][1] + zs[1]) / SB];
+    };
+    // per-plane solid flags (uniform): bit 0 plane pz has a solid node, bit 1 planes pz-1..pz+1 do,
+    // i.e. some pull of plane pz may bounce back
+    auto plane_flags = [&](int pz) __attribute__((always_inline)) {
+        return MASK ? fm.pflags[wrapi(pz, g.nz)] : 0u;
     };
     // rho, s*psi and g_x, g_y of one staged node into ring slot `slot` / g buffer `buf`;
     // returns g_z. h holds the node's pulled populations, m receives (sum h, j).
@@ -181,26 +192,34 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         dgy_p2 = s_gxy[buf][1][e_int + HX] - s_gxy[buf][1][e_int - HX];
     };
     // whole plane z0 + j (prologue, j = -2..2): pull into h, stage, publish
-    auto prologue_plane = [&](int j, C (&h)[27], C (&m)[4]) __attribute__((always_inline)) {
+    auto prologue_body = [&](int j, C (&h)[27], C (&m)[4], auto MP) __attribute__((always_inline)) {
+        constexpr bool MM = decltype(MP)::value;   // pulls of this plane may bounce back
         unsigned zs[3];
         planes(z0 + j, zs);
         const int slot = ((j + 2) % RING) * HP, buf = (j + 2) & 1;
-        const bool solid = solid_at(si, zs);
-        if (!solid) pull_all<S, C, MASK>(Ab, mask, si, zs, h);
+        const uint32_t lm = MM ? links_at(si, zs) : 0u;
+        const bool solid = (lm >> LINK_SELF) & 1u;
+        if (!solid) pull_all<S, C, MM>(Ab, lm, si, zs, h);
         const C gzn = stage(e_int, solid, h, m, slot, buf);
         if (has_halo) {
             C hh[27], mh[4];
-            const bool hs = solid_at(sh, zs);
-            if (!hs) pull_all<S, C, MASK>(Ab, mask, sh, zs, hh);
+            const uint32_t lh = MM ? links_at(sh, zs) : 0u;
+            const bool hs = (lh >> LINK_SELF) & 1u;
+            if (!hs) pull_all<S, C, MM>(Ab, lh, sh, zs, hh);
             stage(e_halo, hs, hh, mh, slot, buf);
         }
         __syncthreads();
         shift_windows(gzn, buf);
     };
+    auto prologue_plane = [&](int j, C (&h)[27], C (&m)[4]) __attribute__((always_inline)) {
+        if (plane_flags(z0 + j) & 2u) prologue_body(j, h, m, std::integral_constant<bool, MASK>{});
+        else prologue_body(j, h, m, std::false_type{});
+    };
 
     // one plane of the march (k = 0 .. tz-1, z = z0 + k): collide plane z from (qa, ma),
     // refill qa with the pulls of plane z+3 as the collided values leave, stage plane z+3
-    auto march = [&](int k, C (&qa)[27], C (&ma)[4]) __attribute__((always_inline)) {
+    auto march_body = [&](int k, C (&qa)[27], C (&ma)[4], auto MP) __attribute__((always_inline)) {
+        constexpr bool MM = decltype(MP)::value;   // pulls of plane z+3 may bounce back
         const int z = z0 + k;
         unsigned zs3[3];
         planes(z + 3, zs3);
@@ -208,10 +227,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const bool need3 = k + 1 < fg.tz;   // plane z+3 feeds the stencil of z+1
         const bool halo = has_halo && need3;
         C hh[27];
-        if (halo && !solid_at(sh, zs3)) pull_all<S, C, MASK>(Ab, mask, sh, zs3, hh);
+        const uint32_t lh = MM && halo ? links_at(sh, zs3) : 0u;
+        if (halo && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
+        const uint32_t l3 = MM ? links_at(si, zs3) : 0u;
 
         const unsigned zoff = (unsigned)(nxy * (z < g.nz ? z : 0)) * SB;
-        const bool act = own && z < g.nz && !(MASK && mask[(si.v[1][1] + zoff) / SB]);
+        const bool act = own && z < g.nz &&
+                         !(MASK && (plane_flags(z) & 1u) && ((fm.links[(si.v[1][1] + zoff) / SB] >> LINK_SELF) & 1u));
         C Sf[3] = {C(0), C(0), C(0)};
         C rho = C(1);
         if (act) {
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         }
         if (halo) {
             C mh[4];
-            stage(e_halo, solid_at(sh, zs3), hh, mh, slot, buf);
+            stage(e_halo, (lh >> LINK_SELF) & 1u, hh, mh, slot, buf);
         }
 
         // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
@@ -288,7 +310,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                         const C hn = om1 * qa[i] + omd * wi + rho * (omega * eqd + fsd);
                         rem -= hn;
                         Bb.store_at(si.v[1][1], zoff + (unsigned)i * Bb.qsb, S(hn));
-                        qa[i] = pull<i, S, C, MASK>(src, mask, si, zs3);
+                        qa[i] = pull<i, S, C, MM>(src, l3, si, zs3);
                         // keep the refill load here: left to itself the scheduler sinks all
                         // loads below the last store, and nothing overlaps their latency
                         __builtin_amdgcn_sched_barrier(0);
@@ -297,14 +319,18 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             });
             // rest population as the remainder: the per-node mass error stays an unbiased rounding
             Bb.store_at(si.v[1][1], zoff, S(rem));
-            qa[0] = pull<0, S, C, MASK>(src, mask, si, zs3);
+            qa[0] = pull<0, S, C, MM>(src, l3, si, zs3);
         } else {
-            pull_all<S, C, MASK>(src, mask, si, zs3, qa);
+            pull_all<S, C, MM>(src, l3, si, zs3, qa);
         }
         C gzn = C(0);
-        if (need3) gzn = stage(e_int, solid_at(si, zs3), qa, ma, slot, buf);
+        if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, qa, ma, slot, buf);
         __syncthreads();
         shift_windows(gzn, buf);
+    };
+    auto march = [&](int k, C (&qa)[27], C (&ma)[4]) __attribute__((always_inline)) {
+        if (plane_flags(z0 + k + 3) & 2u) march_body(k, qa, ma, std::integral_constant<bool, MASK>{});
+        else march_body(k, qa, ma, std::false_type{});
     };
 
     prologue_plane(-2, q0, m0);
@@ -321,13 +347,31 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
 }
 
 template <class S, class C, bool MASK, int TX, int TY>
-void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm,
+void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const FusedMask &fm, const void *prm,
                   const FusedGrid &fg) {
     hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
-                       mask, *(const Params<C> *)prm, fg);
+                       fm, *(const Params<C> *)prm, fg);
+}
+
+__global__ void k_links(const uint8_t *__restrict__ mask, uint32_t *__restrict__ links, Geom g) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const int x = n % g.nx, y = (n / g.nx) % g.ny, z = n / (g.nx * g.ny);
+    uint32_t b = mask[n] ? (1u << LINK_SELF) : 0u;
+    static_for<1, 27>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int s = wrapi(x - Lat<3>::c(i, 0), g.nx) +
+                      g.nx * (wrapi(y - Lat<3>::c(i, 1), g.ny) + g.ny * wrapi(z - Lat<3>::c(i, 2), g.nz));
+        if (mask[s]) b |= 1u << i;
+    });
+    links[n] = b;
 }
 
 }  // namespace
+
+void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g) {
+    hipLaunchKernelGGL(k_links, dim3((g.N + 255) / 256), dim3(256), 0, s, mask, links, g);
+}
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
     FusedGrid f;

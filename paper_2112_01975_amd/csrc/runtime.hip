@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbm2p.h"
 #include "fused.hpp"
@@ -27,6 +28,8 @@ struct lbm_ctx {
     void *A = nullptr, *B = nullptr; // population lattices
     void *rho = nullptr, *gfl = nullptr;
     uint8_t *mask = nullptr;
+    uint32_t *links = nullptr;       // solid-neighbour bits for the fused step (masked only)
+    uint32_t *pflags = nullptr;      // per-plane solid flags for the fused step (masked only)
     double *partials = nullptr, *totals = nullptr;
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
     int nblk = 0;
@@ -61,7 +64,7 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
-    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->partials, c->totals, c->io};
+    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->partials, c->totals, c->io};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -96,7 +99,7 @@ int watchdog(lbm_ctx *c) {
 
 int one_step(lbm_ctx *c) {
     if (c->fused) {
-        c->fused(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->fg);
+        c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags}, params_ptr(c), c->fg);
     } else {
         c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
@@ -173,6 +176,31 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
             free_ctx(c);
             return fail(nullptr, LBM_E_HIP, std::string("mask upload failed: ") + hipGetErrorString(e));
         }
+        if (c->fused) {   // solid-neighbour bits: one word per node instead of 27 mask reads per pull
+            if (hipMalloc((void **)&c->links, N * sizeof(uint32_t)) != hipSuccess) {
+                free_ctx(c);
+                return fail(nullptr, LBM_E_NOMEM, "device allocation of the link mask failed");
+            }
+            fused_links(c->stream, c->mask, c->links, c->g);
+            const int nz = c->g.nz, nxy = c->g.nx * c->g.ny;
+            std::vector<uint32_t> has(nz, 0u), pf(nz, 0u);
+            for (int z = 0; z < nz; ++z)
+                for (int q = 0; q < nxy && !has[z]; ++q) has[z] = p->mask[(size_t)z * nxy + q] ? 1u : 0u;
+            for (int z = 0; z < nz; ++z)
+                pf[z] = has[z] | ((has[(z + nz - 1) % nz] | has[z] | has[(z + 1) % nz]) << 1);
+            if (hipMalloc((void **)&c->pflags, nz * sizeof(uint32_t)) != hipSuccess) {
+                free_ctx(c);
+                return fail(nullptr, LBM_E_NOMEM, "device allocation of the plane flags failed");
+            }
+            if ((e = hipMemcpy(c->pflags, pf.data(), nz * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+                free_ctx(c);
+                return fail(nullptr, LBM_E_HIP, std::string("plane flag upload failed: ") + hipGetErrorString(e));
+            }
+            if ((e = hipStreamSynchronize(c->stream)) != hipSuccess || (e = hipGetLastError()) != hipSuccess) {
+                free_ctx(c);
+                return fail(nullptr, LBM_E_HIP, std::string("link mask failed: ") + hipGetErrorString(e));
+            }
+        }
     }
     *out = c;
     return LBM_OK;
@@ -235,7 +263,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
             c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
         if (c->fused)
-            c->fused(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->fg);
+            c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags}, params_ptr(c), c->fg);
         else
             c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
         HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
