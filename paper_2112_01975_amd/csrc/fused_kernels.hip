@@ -75,7 +75,7 @@ __device__ __forceinline__ void pull_all(const PopBuf<S> &A, uint32_t lm, const 
     });
 }
 
-template <class S, class C, bool MASK, int FTX, int TY>
+template <class S, class C, bool MASK, int FTX, int TY, bool REPULL>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                       FusedMask fm, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
@@ -140,8 +140,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     C gz_m1 = C(0), gz_0 = C(0), gz_p1 = C(0), gz_p2 = C(0);
     C dgx_0 = C(0), dgx_p1 = C(0), dgx_p2 = C(0);
     C dgy_0 = C(0), dgy_p1 = C(0), dgy_p2 = C(0);
-    // populations this thread pulled for planes z, z+1, z+2 and their (sum h, j)
-    C q0[27], q1[27], q2[27];
+    // populations this thread pulled for planes z, z+1, z+2 and their (sum h, j). REPULL
+    // (FP64: three queued planes do not fit in registers) keeps only the moments and pulls
+    // plane z again when it is collided.
+    C q0[27], q1[REPULL ? 1 : 27], q2[REPULL ? 1 : 27];
     C m0[4], m1[4], m2[4];
 
     // byte offsets of planes pz-1, pz, pz+1 (any integer pz)
@@ -234,6 +236,15 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const unsigned zoff = (unsigned)(nxy * (z < g.nz ? z : 0)) * SB;
         const bool act = own && z < g.nz &&
                          !(MASK && (plane_flags(z) & 1u) && ((fm.links[(si.v[1][1] + zoff) / SB] >> LINK_SELF) & 1u));
+        if constexpr (REPULL) {
+            // plane z again: the loads are in flight during the stencil
+            unsigned zsz[3];
+            planes(z, zsz);
+            if (act) {
+                if (MASK && (plane_flags(z) & 2u)) pull_all<S, C, MASK>(Ab, links_at(si, zsz), si, zsz, qa);
+                else pull_all<S, C, false>(Ab, 0u, si, zsz, qa);
+            }
+        }
         C Sf[3] = {C(0), C(0), C(0)};
         C rho = C(1);
         if (act) {
@@ -336,20 +347,34 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     prologue_plane(-2, q0, m0);
     prologue_plane(-1, q0, m0);
     prologue_plane(0, q0, m0);
-    prologue_plane(1, q1, m1);
-    prologue_plane(2, q2, m2);
+    if constexpr (REPULL) {
+        prologue_plane(1, q0, m1);
+        prologue_plane(2, q0, m2);
+    } else {
+        prologue_plane(1, q1, m1);
+        prologue_plane(2, q2, m2);
+    }
+    if constexpr (REPULL) {
 #pragma unroll 1
-    for (int k = 0; k < fg.tz; k += 3) {
-        march(k, q0, m0);
-        if (k + 1 < fg.tz) march(k + 1, q1, m1);
-        if (k + 2 < fg.tz) march(k + 2, q2, m2);
+        for (int k = 0; k < fg.tz; k += 3) {
+            march(k, q0, m0);
+            if (k + 1 < fg.tz) march(k + 1, q0, m1);
+            if (k + 2 < fg.tz) march(k + 2, q0, m2);
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < fg.tz; k += 3) {
+            march(k, q0, m0);
+            if (k + 1 < fg.tz) march(k + 1, q1, m1);
+            if (k + 2 < fg.tz) march(k + 2, q2, m2);
+        }
     }
 }
 
-template <class S, class C, bool MASK, int TX, int TY>
+template <class S, class C, bool MASK, int TX, int TY, bool REPULL>
 void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const FusedMask &fm, const void *prm,
                   const FusedGrid &fg) {
-    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
+    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
                        fm, *(const Params<C> *)prm, fg);
 }
 
@@ -389,12 +414,16 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
 
 namespace {
 template <int TX, int TY> FusedLaunch pick(bool masked) {
-    return masked ? launch_fused<float, float, true, TX, TY> : launch_fused<float, float, false, TX, TY>;
+    return masked ? launch_fused<float, float, true, TX, TY, false> : launch_fused<float, float, false, TX, TY, false>;
 }
 }  // namespace
 
 FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty) {
-    if (fp64) return nullptr;
+    if (fp64) {
+        if (tx == 64 && ty == 8)
+            return masked ? launch_fused<double, double, true, 64, 8, true> : launch_fused<double, double, false, 64, 8, true>;
+        return nullptr;
+    }
     if (tx == 64 && ty == 8) return pick<64, 8>(masked);
     if (tx == 32 && ty == 8) return pick<32, 8>(masked);
     if (tx == 32 && ty == 16) return pick<32, 16>(masked);
