@@ -41,8 +41,15 @@ extern "C" {
 enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
 /* Equations of state of Sec. 3.1: van der Waals (eq vdWEoS), Peng-Robinson
  * (eq PREoS), Redlich-Kwong-Soave (eq RKSEoS), Carnahan-Starling (eq CSEos);
- * LBM_EOS_IDEAL is P = rho/3 = P0, i.e. no non-ideal force (plain LBGK). */
-enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_RKS = 2, LBM_EOS_CS = 3, LBM_EOS_IDEAL = 4 };
+ * LBM_EOS_IDEAL is P = rho/3 = P0, i.e. no non-ideal force (plain LBGK).
+ * LBM_EOS_SC1 / LBM_EOS_SC2 are the Shan-Chen equations of state of the sound-speed
+ * appendix (eqs SCeos, SC1, SC2), P = rho/3 + (G/6) psi^2 with psi = 1 - exp(-rho) or
+ * exp(-1/rho), in the form whose critical points the paper prints (G_c = -4 at
+ * rho_c = ln 2; G_c = -e^2 at rho_c = 1). Their coupling is G = G_c / T_reduced, a
+ * pseudo-temperature with liquid-vapour coexistence for T_reduced < 1; a, b, R and
+ * the acentric factor are not used. */
+enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_RKS = 2, LBM_EOS_CS = 3, LBM_EOS_IDEAL = 4,
+       LBM_EOS_SC1 = 5, LBM_EOS_SC2 = 6 };
 /* LBM_FP64: populations stored and updated in FP64.
  * LBM_FP32_DEV: populations stored as FP32 deviations h_i = f_i - w_i rho_ref and
  * updated in FP32; mass and momentum reductions stay FP64. */
@@ -53,9 +60,10 @@ typedef struct {
     int lattice;            /* LBM_D2Q9 or LBM_D3Q27 */
     int nx, ny, nz;         /* grid; periodic on every axis; nz must be 1 for D2Q9 */
     int eos;                /* LBM_EOS_* */
-    double a, b, R;         /* EOS attraction, co-volume, gas constant */
+    double a, b, R;         /* EOS attraction, co-volume, gas constant (cubic EOS only) */
     double acentric;        /* acentric factor omega' of PR / RKS */
-    double T_reduced;       /* T/Tc; Tc from the printed a(Tc,Pc), b(Tc,Pc) relations */
+    double T_reduced;       /* T/Tc; Tc from the printed a(Tc,Pc), b(Tc,Pc) relations
+                               (Shan-Chen: G_c / G) */
     double kappa;           /* capillary coefficient kappa~ of eq capillary_discrete */
     double tau_liquid;      /* relaxation time, omega = 1/tau; viscosity (tau - 1/2)/3 */
     double tau_vapour;      /* > 0: kinematic viscosity linear in rho between the two
@@ -137,8 +145,8 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]);
 
 /* Thermodynamics of the problem statement, host only (Sec. 3.1). out[0] = rho_v,
  * out[1] = rho_l, out[2] = P_sat from the Maxwell equal-area rule
- * (eq Maxwell_equal_area), out[3] = T = T_reduced * Tc. Returns LBM_E_DOMAIN
- * when the EOS has no van der Waals loop at that temperature. */
+ * (eq Maxwell_equal_area), out[3] = T = T_reduced * Tc (Shan-Chen: the coupling G).
+ * Returns LBM_E_DOMAIN when the EOS has no van der Waals loop at that temperature. */
 int lbm_coexistence(const lbm_params *p, double out[4]);
 
 /* Capillary coefficient for which the flat equilibrium interface of the

@@ -40,7 +40,7 @@
 typedef struct {
     int lattice;            /* 2 = D2Q9, 3 = D3Q27 */
     int nx, ny, nz;
-    int eos;                /* 0 vdW, 1 PR, 2 RKS, 3 CS, 4 ideal (P = rho/3) */
+    int eos;                /* 0 vdW, 1 PR, 2 RKS, 3 CS, 4 ideal (P = rho/3), 5 SC-I, 6 SC-II */
     double a, b, R, acentric, T_reduced;
     double kappa;
     double tau_liquid, tau_vapour, rho_liquid, rho_vapour;
@@ -123,11 +123,27 @@ static double alpha_T(const orc_params *p)
     return s * s;
 }
 
+/* Shan-Chen equations of state (sound-speed appendix, eqs SCeos, SC1, SC2), read as
+ * P = rho/3 + (G/6) psi^2 (the form whose critical points the paper prints), with
+ * G = G_c / T_reduced: G_c = -4 for psi = 1 - exp(-rho), -e^2 for psi = exp(-1/rho). */
+static double sc_coupling(const orc_params *p)
+{
+    return (p->eos == 5 ? -4.0 : -exp(2.0)) / p->T_reduced;
+}
+
 static double eos_pressure(const orc_ctx *x, double rho)
 {
     const orc_params *p = &x->p;
     double RT = p->R * x->T, b = p->b;
     switch (p->eos) {
+    case 5: {
+        double psi = 1.0 - exp(-rho);
+        return rho / 3.0 + sc_coupling(p) / 6.0 * psi * psi;
+    }
+    case 6: {
+        double psi = exp(-1.0 / rho);
+        return rho / 3.0 + sc_coupling(p) / 6.0 * psi * psi;
+    }
     case 0: return rho * RT / (1.0 - b * rho) - p->a * rho * rho;
     case 1: return rho * RT / (1.0 - b * rho) - x->aalpha * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
     case 2: return rho * RT / (1.0 - b * rho) - x->aalpha * rho * rho / (1.0 + b * rho);

@@ -8,6 +8,8 @@ Contents (paper sections cited per function):
   * equations of state: van der Waals, Peng-Robinson, Redlich-Kwong-Soave,
     Carnahan-Starling (Sec. 3.1, eqs vdWEoS, PREoS, RKSEoS, CSEos), with the
     critical temperature taken from the printed a(Tc, Pc), b(Tc, Pc) relations;
+    and the two Shan-Chen equations of state of the sound-speed appendix (eqs SCeos,
+    SC1, SC2) with the coupling G = G_c / T_reduced;
   * the Maxwell equal-area construction for the coexistence densities
     (Sec. 3.1, eq Maxwell_equal_area), evaluated by quadrature of its integral;
   * the flat-interface profile of the second-gradient fluid (Sec. 2.1,
@@ -25,8 +27,18 @@ from dataclasses import dataclass
 import numpy as np
 from scipy import integrate, optimize
 
-VDW, PR, RKS, CS, IDEAL = 0, 1, 2, 3, 4
-EOS_NAMES = {VDW: "vdW", PR: "PR", RKS: "RKS", CS: "CS", IDEAL: "ideal"}
+VDW, PR, RKS, CS, IDEAL, SC1, SC2 = 0, 1, 2, 3, 4, 5, 6
+EOS_NAMES = {VDW: "vdW", PR: "PR", RKS: "RKS", CS: "CS", IDEAL: "ideal", SC1: "SC-I", SC2: "SC-II"}
+
+# Shan-Chen equations of state (appendix on the isothermal sound speed, eqs SCeos, SC1,
+# SC2), read as P = rho/3 + (G/6) psi_SC(rho)^2: the classical form whose critical points
+# are the ones the paper prints (the printed eq SCeos carries P0 = rho/3 in the second
+# term as well, which moves the critical point away from both printed pairs).
+#   SC-I : psi = 1 - exp(-rho),  d2P = 0 at exp(-rho) = 1/2, dP = 0 there at G = -4;
+#   SC-II: psi = exp(-1/rho),    d2P = 0 at rho = 1,         dP = 0 there at G = -e^2.
+# G enters as G = G_c / T_reduced, a pseudo-temperature with coexistence below T_r = 1.
+SC_GC = {SC1: -4.0, SC2: -math.exp(2.0)}
+SC_RHO_SEARCH = 50.0   # no repulsive pole: upper end of the density search
 
 
 @dataclass(frozen=True)
@@ -51,7 +63,12 @@ class Fluid:
             return 0.08664 * a / (0.42748 * b * R)
         if self.eos == CS:       # a = 0.4963 R^2 Tc^2 / Pc, b = 0.18727 R Tc / Pc
             return 0.18727 * a / (0.4963 * b * R)
-        return 1.0 / 3.0         # ideal lattice gas: P = rho / 3 (no critical point)
+        return 1.0 / 3.0         # ideal lattice gas and Shan-Chen: no temperature scale
+
+    @property
+    def G(self) -> float:
+        """Shan-Chen coupling G = G_c / T_reduced (Shan-Chen kinds only)."""
+        return SC_GC[self.eos] / self.T_reduced
 
     @property
     def T(self) -> float:
@@ -77,6 +94,8 @@ class Fluid:
             return 1.0 / self.b
         if self.eos == CS:
             return 4.0 / self.b
+        if self.eos in (SC1, SC2):
+            return SC_RHO_SEARCH
         return math.inf
 
     # -- the equation of state and its density derivative --
@@ -92,6 +111,10 @@ class Fluid:
         if self.eos == CS:
             e = b * rho / 4.0
             return rho * RT * (1.0 + e + e * e - e ** 3) / (1.0 - e) ** 3 - a * rho * rho
+        if self.eos == SC1:
+            return rho / 3.0 + self.G / 6.0 * (1.0 - np.exp(-rho)) ** 2
+        if self.eos == SC2:
+            return rho / 3.0 + self.G / 6.0 * np.exp(-2.0 / rho)
         return rho / 3.0
 
     def dpressure(self, rho):
@@ -115,6 +138,10 @@ class Fluid:
             # d/drho [rho num/den] with de/drho = b/4
             g = num / den + rho * (b / 4.0) * (dnum * den + 3.0 * num * (1.0 - e) ** 2) / (den * den)
             return RT * g - 2.0 * a * rho
+        if self.eos == SC1:      # psi' = exp(-rho)
+            return 1.0 / 3.0 + self.G / 3.0 * (1.0 - np.exp(-rho)) * np.exp(-rho)
+        if self.eos == SC2:      # psi' = exp(-1/rho) / rho^2
+            return 1.0 / 3.0 + self.G / 3.0 * np.exp(-2.0 / rho) / (rho * rho)
         return np.full_like(rho, 1.0 / 3.0)
 
 

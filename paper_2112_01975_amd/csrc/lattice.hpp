@@ -57,7 +57,7 @@ __host__ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // ---------------------------------------------------------------- EOS (Sec. 3.1)
-enum { EOS_VDW = 0, EOS_PR = 1, EOS_RKS = 2, EOS_CS = 3, EOS_IDEAL = 4 };
+enum { EOS_VDW = 0, EOS_PR = 1, EOS_RKS = 2, EOS_CS = 3, EOS_IDEAL = 4, EOS_SC1 = 5, EOS_SC2 = 6 };
 
 // Reciprocal and square root in compute precision: FP32 uses the hardware
 // v_rcp_f32 / v_sqrt_f32 (1 ulp); FP64 keeps the correctly rounded operations.
@@ -65,11 +65,13 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float sqrt_c(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_c(double x) { return sqrt(x); }
+__device__ __forceinline__ float exp_c(float x) { return expf(x); }
+__device__ __forceinline__ double exp_c(double x) { return exp(x); }
 
 template <class C> struct Eos {
     int kind;
     C RT;   // R * T with T = T_reduced * Tc
-    C aa;   // a * alpha(T) (alpha = 1 for vdW and CS)
+    C aa;   // a * alpha(T) (alpha = 1 for vdW and CS); the coupling G for Shan-Chen
     C b;
 
     // P(rho) with a single reciprocal of the combined denominator
@@ -90,6 +92,13 @@ template <class C> struct Eos {
             const C e = C(0.25) * b * r;
             const C me = one - e;
             return r * RT * (one + e + e * e - e * e * e) * rcp(me * me * me) - aa * r * r;
+        }
+        case EOS_SC1: {   // P = rho/3 + (G/6) psi^2, psi = 1 - exp(-rho)
+            const C s = one - exp_c(-r);
+            return r * C(1.0 / 3.0) + aa * C(1.0 / 6.0) * s * s;
+        }
+        case EOS_SC2: {   // psi = exp(-1/rho): psi^2 = exp(-2/rho)
+            return r * C(1.0 / 3.0) + aa * C(1.0 / 6.0) * exp_c(C(-2) * rcp(r));
         }
         default: return r * C(1.0 / 3.0);
         }

@@ -363,7 +363,8 @@ int lbm_coexistence(const lbm_params *p, double out[4]) {
     HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
     double rv, rl, ps;
     if (coexistence(e, &rv, &rl, &ps)) return fail(nullptr, LBM_E_DOMAIN, "no van der Waals loop at this temperature");
-    out[0] = rv; out[1] = rl; out[2] = ps; out[3] = e.T;
+    out[0] = rv; out[1] = rl; out[2] = ps;
+    out[3] = (p->eos == LBM_EOS_SC1 || p->eos == LBM_EOS_SC2) ? e.aa : e.T;   // Shan-Chen: the coupling G
     return LBM_OK;
 }
 

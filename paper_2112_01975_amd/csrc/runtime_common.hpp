@@ -29,10 +29,14 @@ inline bool validate_params(const lbm_params *p, std::string *why) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { *why = "grid sizes must be >= 1"; return false; }
     if (p->lattice == LBM_D2Q9 && p->nz != 1) { *why = "D2Q9 requires nz == 1"; return false; }
     if ((double)p->nx * p->ny * p->nz >= 2147483647.0) { *why = "grid larger than 2^31 nodes"; return false; }
-    if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_IDEAL) { *why = "unknown equation of state"; return false; }
-    if (p->eos != LBM_EOS_IDEAL) {
+    if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_SC2) { *why = "unknown equation of state"; return false; }
+    const bool shan_chen = p->eos == LBM_EOS_SC1 || p->eos == LBM_EOS_SC2;
+    if (p->eos != LBM_EOS_IDEAL && !shan_chen) {
         if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0)) { *why = "EOS parameters a, b, R must be > 0"; return false; }
-        if (!(p->T_reduced > 0)) { *why = "T_reduced must be > 0"; return false; }
+    }
+    if (p->eos != LBM_EOS_IDEAL && !(p->T_reduced > 0 && isfinite(p->T_reduced))) {
+        *why = "T_reduced must be > 0";
+        return false;
     }
     if (!(p->kappa >= 0) || !isfinite(p->kappa)) { *why = "kappa must be finite and >= 0"; return false; }
     if (!(p->tau_liquid > 0.5) || !isfinite(p->tau_liquid)) { *why = "tau_liquid must be > 1/2"; return false; }

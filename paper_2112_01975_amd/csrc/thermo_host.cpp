@@ -19,9 +19,14 @@ double critical_temperature(int eos, double a, double b, double R) {
     case 1: return 0.0778 * a / (0.45724 * b * R);     // PR
     case 2: return 0.08664 * a / (0.42748 * b * R);    // RKS
     case 3: return 0.18727 * a / (0.4963 * b * R);     // CS
-    default: return 1.0 / 3.0;
+    default: return 1.0 / 3.0;                         // ideal gas, Shan-Chen: no temperature scale
     }
 }
+
+// Shan-Chen critical couplings (sound-speed appendix): P = rho/3 + (G/6) psi^2 has
+// dP = d2P = 0 at exp(-rho) = 1/2, G = -4 for psi = 1 - exp(-rho) and at rho = 1,
+// G = -e^2 for psi = exp(-1/rho)
+static double sc_critical_coupling(int eos) { return eos == 5 ? -4.0 : -exp(2.0); }
 
 double alpha_of(int eos, double acentric, double T_reduced) {
     double m;
@@ -35,7 +40,7 @@ double alpha_of(int eos, double acentric, double T_reduced) {
 HostEos::HostEos(int eos_, double a_, double b_, double R_, double acentric, double T_reduced)
     : eos(eos_), a(a_), b(b_), R(R_) {
     T = T_reduced * critical_temperature(eos, a, b, R);
-    aa = a * alpha_of(eos, acentric, T_reduced);
+    aa = (eos == 5 || eos == 6) ? sc_critical_coupling(eos) / T_reduced : a * alpha_of(eos, acentric, T_reduced);
 }
 
 double HostEos::P(double r) const {
@@ -48,6 +53,11 @@ double HostEos::P(double r) const {
         double e = 0.25 * b * r, m = 1.0 - e;
         return r * RT * (1.0 + e + e * e - e * e * e) / (m * m * m) - aa * r * r;
     }
+    case 5: {
+        double s = 1.0 - exp(-r);
+        return r / 3.0 + aa / 6.0 * s * s;
+    }
+    case 6: return r / 3.0 + aa / 6.0 * exp(-2.0 / r);
     default: return r / 3.0;
     }
 }
@@ -72,6 +82,8 @@ double HostEos::dP(double r) const {
         double Z = num / (m * m * m), dZ = dnum / (m * m * m) + 3.0 * num / (m * m * m * m);
         return RT * (Z + e * dZ) - 2.0 * aa * r;
     }
+    case 5: return 1.0 / 3.0 + aa / 3.0 * (1.0 - exp(-r)) * exp(-r);        // psi psi', psi' = exp(-rho)
+    case 6: return 1.0 / 3.0 + aa / 3.0 * exp(-2.0 / r) / (r * r);          // psi' = exp(-1/rho)/rho^2
     default: return 1.0 / 3.0;
     }
 }
@@ -79,6 +91,7 @@ double HostEos::dP(double r) const {
 double HostEos::rho_max() const {
     if (eos == 0 || eos == 1 || eos == 2) return 1.0 / b;
     if (eos == 3) return 4.0 / b;
+    if (eos == 5 || eos == 6) return 50.0;   // no repulsive pole: upper end of the density search
     return INFINITY;
 }
 

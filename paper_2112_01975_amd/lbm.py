@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm2p.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_DOMAIN, LBM_E_DIVERGED, LBM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 LBM_D2Q9, LBM_D3Q27 = 0, 1
-LBM_EOS_VDW, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_CS, LBM_EOS_IDEAL = 0, 1, 2, 3, 4
+LBM_EOS_VDW, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_CS, LBM_EOS_IDEAL, LBM_EOS_SC1, LBM_EOS_SC2 = 0, 1, 2, 3, 4, 5, 6
 LBM_FP64, LBM_FP32_DEV = 0, 1
 
 EXPORTED = [

@@ -13,7 +13,7 @@ import lbm_inputs as L
 from oracle import oracle as O
 from oracle import thermo as T
 
-EOS_OF = {T.VDW: 0, T.PR: 1, T.RKS: 2, T.CS: 3, T.IDEAL: 4}
+EOS_OF = {T.VDW: 0, T.PR: 1, T.RKS: 2, T.CS: 3, T.IDEAL: 4, T.SC1: 5, T.SC2: 6}
 
 
 @dataclass

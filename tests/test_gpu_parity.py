@@ -46,10 +46,11 @@ def test_static_drop_d2q9_ragged_fp64():
     _cmp64(case, rho0, u0, 400)
 
 
-@pytest.mark.parametrize("eos,a,om,tr", [(T.VDW, 0.02, 0.0, 0.7), (T.PR, 0.005, 0.344, 0.6),
-                                        (T.RKS, 0.01, 0.344, 0.7), (T.CS, 0.005, 0.0, 0.7)])
-def test_every_eos_d2q9_fp64(eos, a, om, tr):
-    case = Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr)
+@pytest.mark.parametrize("eos,a,om,tr,kappa", [(T.VDW, 0.02, 0.0, 0.7, 0.02), (T.PR, 0.005, 0.344, 0.6, 0.02),
+                                              (T.RKS, 0.01, 0.344, 0.7, 0.02), (T.CS, 0.005, 0.0, 0.7, 0.02),
+                                              (T.SC1, 0.0, 0.0, 0.9, 0.05), (T.SC2, 0.0, 0.0, 0.9, 0.05)])
+def test_every_eos_d2q9_fp64(eos, a, om, tr, kappa):
+    case = Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr, kappa=kappa)
     rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 7)
     _cmp64(case, rho0, u0, 300)
 
@@ -66,6 +67,19 @@ def test_drop_d3q27_periodic_fp64():
     case = Case(3, 70, 36, 20, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
     rho0, u0 = drop_case_inputs(case, 8.0, 5.0, 1e-5, 1003, centre=(35.0, 18.0, 10.0))
     _cmp64(case, rho0, u0, 100)
+
+
+@pytest.mark.parametrize("eos", [T.SC1, T.SC2])
+def test_shan_chen_drop_d3q27_fp64_and_fp32(eos):
+    # Shan-Chen EOS through the fused D3Q27 kernels: FP64 against the oracle element by
+    # element, FP32 deviation storage on the bulk densities
+    case = Case(3, 70, 20, 24, eos=eos, T_reduced=0.9, kappa=0.05)
+    rho0, u0 = drop_case_inputs(case, 6.0, 3.0, 1e-4, 1004, centre=(35.0, 10.0, 12.0))
+    _cmp64(case, rho0, u0, 100)
+    rv, _ = case.coexistence()
+    r32, _, _ = run_gpu(case, rho0, u0, 100, precision=1, rho_ref=rv)
+    r64, _, _ = run_oracle(case, rho0, u0, 100)
+    assert max_rel(r32, r64) < 1e-4
 
 
 def test_textured_wall_d3q27_variable_viscosity_fp64():

@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("eos,a,om,tr", [(0, 9 / 49, 0.0, 0.9), (0, 9 / 49, 0.0, 0.55), (1, 2 / 49, 0.344, 0.6),
-                                         (1, 2 / 49, 0.344, 0.5), (2, 0.01, 0.344, 0.7), (3, 0.01, 0.0, 0.7)])
+                                         (1, 2 / 49, 0.344, 0.5), (2, 0.01, 0.344, 0.7), (3, 0.01, 0.0, 0.7),
+                                         (5, 0.0, 0.0, 0.9), (5, 0.0, 0.0, 0.6), (6, 0.0, 0.0, 0.9), (6, 0.0, 0.0, 0.6)])
 def test_host_coexistence_matches_oracle(eos, a, om, tr):
     import paper_2112_01975_amd as P
     p = P.Params(P.LBM_D3Q27, 4, 4, 4, eos, a, 2 / 21, 1.0, om, tr)
@@ -38,7 +39,7 @@ def test_host_coexistence_matches_oracle(eos, a, om, tr):
     fl = T.Fluid(eos, a, 2 / 21, tr, 1.0, om)
     ov, ol, ops = T.coexistence(fl)
     assert abs(rv / ov - 1) < 1e-10 and abs(rl / ol - 1) < 1e-10 and abs(ps / ops - 1) < 1e-9
-    assert abs(Tt / fl.T - 1) < 1e-15
+    assert abs(Tt / (fl.G if eos in (T.SC1, T.SC2) else fl.T) - 1) < 1e-15
     k = P.lbm_kappa_for_width(p, 5.0)
     assert abs(k / T.kappa_for_width(fl, 5.0) - 1) < 1e-8
 

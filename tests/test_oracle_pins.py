@@ -25,6 +25,7 @@ wrong weight) fails at least one of them:
 import math
 
 import numpy as np
+from scipy import integrate, optimize
 import pytest
 
 import lbm_inputs as L
@@ -179,7 +180,7 @@ def test_printed_critical_constants_are_near_inflection(eos, om):
     assert abs(dmin) < 2e-3 * fl.R * fl.T
 
 
-@pytest.mark.parametrize("eos", [T.VDW, T.PR, T.RKS, T.CS])
+@pytest.mark.parametrize("eos", [T.VDW, T.PR, T.RKS, T.CS, T.SC1, T.SC2])
 def test_oracle_c_eos_matches_thermo(eos):
     cfg = O.Config(3, 2, 2, 2, eos, 0.03, B21, 1.0, 0.344, 0.7)
     orc = O.Oracle(cfg)
@@ -216,6 +217,62 @@ def test_maxwell_pr_equal_chemical_potential(tr):
     fl = T.Fluid(T.PR, 2 / 49, B21, tr, 1.0, 0.344)
     rv, rl, ps = T.coexistence(fl)
     assert abs(_mu_pr(fl, rv) - _mu_pr(fl, rl)) < 1e-10 * abs(_mu_pr(fl, rl))
+
+
+# Shan-Chen equations of state (sound-speed appendix, eqs SCeos, SC1, SC2): the paper
+# prints the critical points (G_c, rho_c) = (-4, 0.6931) and (-7.389, 1). The oracle's P
+# is linear in G, P = rho/3 + G f(rho); the critical point is where f'' = 0 and
+# dP/drho = 1/3 + G f' = 0, found here numerically from the oracle's own dP/drho.
+@pytest.mark.parametrize("eos,gc_printed,rc_printed", [(T.SC1, -4.0, 0.6931), (T.SC2, -7.389, 1.0)])
+def test_shan_chen_printed_critical_points(eos, gc_printed, rc_printed):
+    fl = T.Fluid(eos, 0.0, 0.0, 1.0)
+    G = fl.G
+    fp = lambda r: (float(fl.dpressure(r)) - 1.0 / 3.0) / G          # f'(rho)
+    h = 1e-5
+    fpp = lambda r: (fp(r + h) - fp(r - h)) / (2 * h)                   # f''(rho)
+    rc = optimize.brentq(fpp, 0.3, 3.0, xtol=1e-14)
+    gc = -1.0 / (3.0 * fp(rc))
+    assert abs(rc - rc_printed) < 5e-5, rc
+    assert abs(gc - gc_printed) < 5e-4, gc
+    # and the oracle's coupling at T_reduced = 1 is that critical coupling
+    assert abs(G - gc) < 1e-8
+
+
+def test_shan_chen_literal_eos_misses_the_printed_critical_point():
+    # the printed eq SCeos, taken literally with P0 = rho/3 in both terms:
+    # P = rho/3 + (rho/3)(G/2) psi^2; at the printed SC-I critical point it is not critical
+    G, rc = -4.0, math.log(2.0)
+    P = lambda r: r / 3 + (r / 3) * (G / 2) * (1 - math.exp(-r)) ** 2
+    h = 1e-4
+    d1 = (P(rc + h) - P(rc - h)) / (2 * h)
+    d2 = (P(rc + h) - 2 * P(rc) + P(rc - h)) / (h * h)
+    assert abs(d1) > 0.05 and abs(d2) > 0.05
+
+
+@pytest.mark.parametrize("eos,tr", [(T.SC1, 0.9), (T.SC1, 0.6), (T.SC2, 0.9), (T.SC2, 0.6)])
+def test_maxwell_shan_chen_equal_pressure_and_chemical_potential(eos, tr):
+    # mu_l - mu_v = integral of P'(rho)/rho over [rho_v, rho_l] vanishes at coexistence
+    fl = T.Fluid(eos, 0.0, 0.0, tr)
+    rv, rl, ps = T.coexistence(fl)
+    assert abs(float(fl.pressure(rv)) - ps) < 1e-12 * ps and abs(float(fl.pressure(rl)) - ps) < 1e-12 * ps
+    dmu, _ = integrate.quad(lambda r: float(fl.dpressure(r)) / r, rv, rl, epsabs=1e-14, epsrel=1e-13, limit=500)
+    scale, _ = integrate.quad(lambda r: abs(float(fl.dpressure(r))) / r, rv, rl, limit=500)
+    assert abs(dmu) < 1e-10 * scale
+
+
+def test_shan_chen_flat_interface_reaches_near_maxwell_densities():
+    # dynamics of the full oracle step with the Shan-Chen EOS (kappa 0.05, T_r 0.9):
+    # the bulk densities settle within 0.3% of the Maxwell construction (the model's
+    # thermodynamic consistency at interfaces ~3 nodes wide)
+    for eos, tol in ((T.SC1, 1e-3), (T.SC2, 4e-3)):
+        fl = T.Fluid(eos, 0.0, 0.0, 0.9)
+        rv, rl, _ = T.coexistence(fl)
+        cfg = O.Config(2, 64, 8, 1, eos, 0.0, 0.0, 1.0, 0.0, 0.9, 0.05, 0.8)
+        orc = O.Oracle(cfg).init(L.flat_slab(64, 8, 1, rl, rv, 3.0, noise=1e-4, seed=7))
+        orc.step(3000)
+        r, _, _ = orc.moments()
+        r2 = r.reshape(8, 64)
+        assert abs(r2[:, 32].mean() / rl - 1) < tol and abs(r2[:, 0].mean() / rv - 1) < tol
 
 
 def test_corresponding_states_and_critical_limit():
@@ -270,6 +327,8 @@ CASES = [
     (3, (4, 5, 6), T.PR, 0.005, 0.344, False),
     (3, (5, 4, 6), T.RKS, 0.01, 0.3, True),
     (3, (3, 3, 3), T.VDW, 0.02, 0.0, True),
+    (2, (1, 6, 5), T.SC1, 0.0, 0.0, True),
+    (3, (3, 4, 5), T.SC2, 0.0, 0.0, False),
 ]
 
 
