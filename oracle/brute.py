@@ -49,11 +49,13 @@ class BruteForce:
     """Tiny-grid FP64 reference: state f[(c)] on a grid of shape (ny, nx) or (nz, ny, nx)."""
 
     def __init__(self, D, shape, fluid: Fluid, kappa, tau, rho_wall=0.0, mask=None,
-                 tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0):
+                 tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0, accel=(0.0, 0.0, 0.0), rho_wall_field=None):
         self.D, self.shape = D, tuple(shape)
         self.fluid, self.kappa = fluid, kappa
         self.tau, self.tau_v, self.rl, self.rv = tau, tau_vapour, rho_liquid, rho_vapour
-        self.rho_wall = rho_wall
+        # per-node wall densities if given (only solid entries matter), else one value
+        self.rho_wall = rho_wall if rho_wall_field is None else np.asarray(rho_wall_field, float).reshape(shape)
+        self.accel = [float(g) for g in accel][:D]      # body-force acceleration: source + rho g
         self.solid = np.zeros(self.shape, bool) if mask is None else mask.reshape(self.shape).astype(bool)
         self.vel = _velocities(D)
         self.wcube = AXIS_W
@@ -81,7 +83,8 @@ class BruteForce:
         return 1.0 / (3.0 * (nv + (nl - nv) * s) + 0.5)
 
     def _source(self, rho):
-        """S = -F for eq Kforce_final on a density field (solid nodes already hold rho_w)."""
+        """S = -F for eq Kforce_final plus the body force rho g, on a density field (solid
+        nodes already hold rho_w)."""
         D = self.D
         P = self.fluid.pressure(rho)
         P0 = rho / 3.0
@@ -98,7 +101,8 @@ class BruteForce:
                     Fpsi[a] += c[a] * tp
                     Fcap[a] += c[a] * tc
         F = 2.0 * sgn * psi * Fpsi + self.kappa * rho * Fcap
-        return np.where(self.solid, 0.0, -F)
+        S = -F + np.stack([rho * g for g in self.accel])
+        return np.where(self.solid, 0.0, S)
 
     def fields(self):
         D = self.D

@@ -47,6 +47,8 @@ typedef struct {
     double rho_wall;
     int variant;            /* test-only switches: 1 literal zeta*, 2 literal force sign, 4 no Phi,
                                8 initial velocity taken as the bare u */
+    double accel[3];        /* body-force acceleration g: the source gains rho g (Sec. 4.2) */
+    const double *rho_wall_field; /* NULL or [N]: wall density of each solid node (copied) */
 } orc_params;
 
 typedef struct {
@@ -58,6 +60,7 @@ typedef struct {
     int opp[27];
     double T, aalpha;
     unsigned char *mask;    /* NULL = fully periodic */
+    double *rho_wf;         /* NULL or [N]: per-node wall density */
     double *f, *fn;         /* [Q][N], pre-collision populations at time t */
     double *rho, *u, *psi, *sgn, *g, *S; /* u, g, S: [3][N] */
 } orc_ctx;
@@ -201,7 +204,7 @@ void orc_destroy(void *h)
     orc_ctx *x = (orc_ctx *)h;
     if (!x) return;
     free(x->mask); free(x->f); free(x->fn); free(x->rho); free(x->u);
-    free(x->psi); free(x->sgn); free(x->g); free(x->S);
+    free(x->psi); free(x->sgn); free(x->g); free(x->S); free(x->rho_wf);
     free(x);
 }
 
@@ -235,6 +238,12 @@ void *orc_create(const orc_params *p, const unsigned char *mask)
         if (!x->mask) { orc_destroy(x); return NULL; }
         memcpy(x->mask, mask, N);
     }
+    x->p.rho_wall_field = NULL;
+    if (p->rho_wall_field) {
+        x->rho_wf = (double *)malloc(N * sizeof(double));
+        if (!x->rho_wf) { orc_destroy(x); return NULL; }
+        memcpy(x->rho_wf, p->rho_wall_field, N * sizeof(double));
+    }
     return x;
 }
 
@@ -264,7 +273,10 @@ int orc_init(void *h, const double *rho0, const double *U0)
     return 0;
 }
 
-/* steps 1-4: moments, EOS, pseudo-potential, g = rho u^3, source S = -F_K */
+/* virtual density of solid node n (Sec. 4.5): per node if given, else rho_wall */
+static double wall_rho(const orc_ctx *x, long n) { return x->rho_wf ? x->rho_wf[n] : x->p.rho_wall; }
+
+/* steps 1-4: moments, EOS, pseudo-potential, g = rho u^3, source S = -F_K + rho g */
 static void fields(orc_ctx *x)
 {
     long N = x->N;
@@ -274,7 +286,7 @@ static void fields(orc_ctx *x)
     for (long n = 0; n < N; ++n) {
         double r, j[3] = {0, 0, 0};
         if (solid(x, n)) {
-            r = p->rho_wall;
+            r = wall_rho(x, n);
         } else {
             r = 0.0;
             for (int i = 0; i < Q; ++i) {
@@ -304,7 +316,7 @@ static void fields(orc_ctx *x)
         }
         for (int a = 0; a < 3; ++a) {
             double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + p->kappa * x->rho[n] * Fc[a];
-            double s = (p->variant & 2) ? F : -F;
+            double s = ((p->variant & 2) ? F : -F) + x->rho[n] * p->accel[a];
             x->S[a * N + n] = (solid(x, n) || a >= D) ? 0.0 : s;
         }
     }
@@ -315,7 +327,7 @@ static void source_of_density(orc_ctx *x, const double *rho)
 {
     long N = x->N;
     for (long n = 0; n < N; ++n) {
-        double r = solid(x, n) ? x->p.rho_wall : rho[n];
+        double r = solid(x, n) ? wall_rho(x, n) : rho[n];
         x->rho[n] = r;
         double P = eos_pressure(x, r), P0 = r / 3.0;
         x->psi[n] = sqrt(fabs(P - P0));
@@ -331,7 +343,7 @@ static void source_of_density(orc_ctx *x, const double *rho)
         }
         for (int a = 0; a < 3; ++a) {
             double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * x->rho[n] * Fc[a];
-            double s = (x->p.variant & 2) ? F : -F;
+            double s = ((x->p.variant & 2) ? F : -F) + x->rho[n] * x->p.accel[a];
             x->S[a * N + n] = (solid(x, n) || a >= x->D) ? 0.0 : s;
         }
     }

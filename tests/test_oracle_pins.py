@@ -358,7 +358,8 @@ def test_mass_exact_and_momentum_changes_by_source(D, masked):
     rv, rl, _ = T.coexistence(fl)
     rho, u = L.random_state(nx * ny * nz, D, rv, 0.5 * rl, 0.03, 5)
     mask = L.random_mask(nx, ny, nz, 0.1, 9) if masked else None
-    cfg = O.Config(D, nx, ny, nz, T.PR, 0.005, B21, 1.0, 0.344, 0.6, 0.02, 0.7, rho_wall=rv)
+    cfg = O.Config(D, nx, ny, nz, T.PR, 0.005, B21, 1.0, 0.344, 0.6, 0.02, 0.7, rho_wall=rv,
+                   accel=(2e-5, -1e-5, 3e-5))
     orc = O.Oracle(cfg, mask).init(rho, u)
     _, _, t0 = orc.moments()
     S = orc.source()
@@ -368,6 +369,112 @@ def test_mass_exact_and_momentum_changes_by_source(D, masked):
     if not masked:
         for a in range(D):
             assert abs((t1[1 + a] - t0[1 + a]) - S[a].sum()) < 1e-12 * t0[0]
+
+
+# ------------------------------------------------------------------ body force (Sec. 4.2, Appendix F)
+def _channel(nx, H, nwall=2):
+    """Solid rows at both ends of y (nwall each): fluid rows nwall .. nwall+H-1, walls at
+    y = 0 and y = H in the frame y_w = row - nwall + 1/2 (halfway bounce-back)."""
+    ny = H + 2 * nwall
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[:nwall] = 1
+    mask[-nwall:] = 1
+    yw = np.arange(ny) - nwall + 0.5
+    return ny, mask, yw
+
+
+@pytest.mark.parametrize("tau,H", [(0.8, 16), (0.8, 32), (0.5 + math.sqrt(3) / 4, 24), (1.2, 32)])
+def test_body_force_poiseuille_single_phase_closed_form(tau, H):
+    # ideal gas, kappa = 0, gravity along x between halfway bounce-back walls. Steady state
+    # of the Navier-Stokes limit: u = g y (H - y) / (2 nu). Halfway bounce-back adds a
+    # uniform slip 2 g ((tau - 1/2)^2 - 3/16) / (tau - 1/2), zero at tau = 1/2 + sqrt(3)/4,
+    # so the discrete steady state is the parabola plus that constant, to rounding.
+    g, nx = 1e-6, 4
+    ny, mask, yw = _channel(nx, H, 1)
+    cfg = O.Config(2, nx, ny, 1, T.IDEAL, 0.0, 0.0, 1.0, 0.0, 1.0, 0.0, tau, rho_wall=1.0, accel=(g, 0.0, 0.0))
+    nu = (tau - 0.5) / 3
+    steps = int(26 * H * H / (math.pi ** 2 * nu))
+    _, U, _ = O.Oracle(cfg, mask.ravel()).init(np.ones(nx * ny)).step(steps).moments()
+    y = yw[1:-1]
+    ux = U[0].reshape(ny, nx)[1:-1]
+    slip = 2 * g * ((tau - 0.5) ** 2 - 3 / 16) / (tau - 0.5)
+    ua = g * y * (H - y) / (2 * nu) + slip
+    assert np.abs(ux - ua[:, None]).max() < 1e-9 * ua.max()
+    assert np.abs(U[1]).max() < 1e-15
+
+
+def _layered_u(y, H, h, g, ml, mv, rl, rv):
+    """Steady layered Poiseuille flow (Sec. 4.2, eqs Poiseuille_odes with their boundary
+    conditions; Appendix F): liquid 0 <= y <= h, vapour above. b_l and c_v are the printed
+    coefficients; b_v is the one that solves the printed system (the printed b_v lacks the
+    term -h^2 mu_v rho_l in its numerator)."""
+    al, av = -rl * g / (2 * ml), -rv * g / (2 * mv)
+    den = H * ml - h * ml + h * mv
+    bl = g * (H * H * ml * rv - 2 * h * h * ml * rl + h * h * ml * rv + h * h * mv * rl + 2 * H * h * ml * rl
+              - 2 * H * h * ml * rv) / (2 * ml * den)
+    bv = g * (H * H * ml * rv - h * h * ml * rv - h * h * mv * rl + 2 * h * h * mv * rv) / (2 * mv * den)
+    cv = g * H * (h * h * ml * rv + h * h * mv * rl - 2 * h * h * mv * rv - H * h * ml * rv + H * h * mv * rv) / (2 * mv * den)
+    return np.where(y <= h, al * y * y + bl * y, av * y * y + bv * y + cv), (al, bl, av, bv, cv)
+
+
+def test_layered_poiseuille_coefficients_solve_the_printed_system():
+    H, h, g, ml, mv, rl, rv = 200.0, 100.0, 1e-8, 0.7, 0.07, 7.0, 0.7
+    _, (al, bl, av, bv, cv) = _layered_u(np.array([0.0]), H, h, g, ml, mv, rl, rv)
+    ul = lambda y: al * y * y + bl * y
+    uv = lambda y: av * y * y + bv * y + cv
+    scale = abs(bl) * H
+    assert abs(uv(H)) < 1e-12 * scale                                        # no slip at the top
+    assert abs(ul(h) - uv(h)) < 1e-12 * scale                                # velocity continuity
+    assert abs(ml * (2 * al * h + bl) - mv * (2 * av * h + bv)) < 1e-12 * ml * abs(bl)   # stress continuity
+    # the printed b_v violates all three
+    bv_printed = g * (H * H * ml * rv - h * h * ml * rv + 2 * h * h * mv * rv) / (2 * mv * (H * ml - h * ml + h * mv))
+    assert abs(av * H * H + bv_printed * H + cv) > 1e-3 * scale
+
+
+def test_layered_poiseuille_two_phase_matches_closed_form():
+    # van der Waals at T/Tc = 0.77 (density ratio 9.98, the printed configuration (a)
+    # ratio 10.1), kappa 0.02 with a for W = 4, equal kinematic viscosities (mu_l/mu_v =
+    # rho_l/rho_v), liquid in the lower half of a channel of width 100 between walls whose
+    # virtual densities are the adjacent phases (two solid rows each, so both force rings
+    # stay inside the wall). Steady profile within 2% of the sharp-interface closed form.
+    fl0 = T.Fluid(T.VDW, A9, B21, 0.77)
+    a = A9 * 0.02 / T.kappa_for_width(fl0, 4.0)
+    rv, rl, _ = T.coexistence(T.Fluid(T.VDW, a, B21, 0.77))
+    H, nx, tau, g = 100, 5, 1.0, 1e-7
+    ny, mask, yw = _channel(nx, H, 2)
+    wall = np.where(np.arange(ny) < ny // 2, rl, rv)[:, None] * np.ones((1, nx))
+    rho = 0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2 * (yw - H / 2) / 4.0)
+    cfg = O.Config(2, nx, ny, 1, T.VDW, a, B21, 1.0, 0.0, 0.77, 0.02, tau, rho_wall=rv, accel=(g, 0.0, 0.0),
+                   rho_wall_field=wall.ravel())
+    nu = (tau - 0.5) / 3
+    orc = O.Oracle(cfg, mask.ravel()).init(np.repeat(rho[:, None], nx, axis=1).ravel())
+    orc.step(int(12 * H * H / (math.pi ** 2 * nu)))
+    r, U, _ = orc.moments()
+    y = yw[2:-2]
+    ux = U[0].reshape(ny, nx)[2:-2, 0]
+    ua, _ = _layered_u(y, H, H / 2, g, rl * nu, rv * nu, rl, rv)
+    assert np.abs(ux - ua).max() < 0.02 * ua.max()
+    r2 = r.reshape(ny, nx)
+    assert abs(r2[2, 0] / rl - 1) < 1e-3 and abs(r2[-3, 0] / rv - 1) < 1e-2   # no wall layer
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_oracle_matches_numpy_step_with_body_force_and_wall_field(D):
+    nz, ny, nx = (1, 7, 6) if D == 2 else (4, 5, 6)
+    fl = T.Fluid(T.VDW, 0.02, B21, 0.7)
+    rv, rl, _ = T.coexistence(fl)
+    N = nx * ny * nz
+    rho, u = L.random_state(N, D, rv, rl, 0.05, 12)
+    mask = L.random_mask(nx, ny, nz, 0.2, 4)
+    wf = np.random.default_rng(2).uniform(rv, rl, N)
+    g = (3e-5, -2e-5, 1e-5)
+    cfg = O.Config(D, nx, ny, nz, T.VDW, 0.02, B21, 1.0, 0.0, 0.7, 0.02, 0.8, rho_wall=rv, accel=g, rho_wall_field=wf)
+    r1, U1, _ = O.Oracle(cfg, mask).init(rho, u).step(10).moments()
+    shape = (ny, nx) if D == 2 else (nz, ny, nx)
+    bf = B.BruteForce(D, shape, fl, 0.02, 0.8, rho_wall=rv, mask=mask, accel=g, rho_wall_field=wf)
+    r2, U2 = bf.init(rho, u).step(10).moments()
+    assert np.abs(r1 - r2).max() < 1e-13 * np.abs(r2).max()
+    assert np.abs(U1 - U2).max() < 1e-13
 
 
 # ------------------------------------------------------------------ physics
