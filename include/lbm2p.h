@@ -76,6 +76,14 @@ typedef struct {
     int check_every;        /* watchdog period in steps inside lbm_step: > 0 every
                                check_every steps and at the end, 0 at the end only,
                                < 0 never */
+    double accel[3];        /* body-force acceleration g (layered Poiseuille flow, Sec. 4.2):
+                               the momentum source gains rho g, so U and the equilibria
+                               carry it as they carry the Korteweg force; finite; z = 0
+                               for D2Q9 */
+    const double *rho_wall_field; /* nullable host array [N]: virtual density of each solid
+                               node (> 0 where mask is set), replacing rho_wall, so that
+                               walls of different wettability or walls touching different
+                               phases can coexist; copied at create */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

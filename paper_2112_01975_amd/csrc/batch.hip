@@ -64,7 +64,7 @@ __device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, i
             const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
             C rho, ga[3] = {C(0), C(0), C(0)};
             if (mask && mask[n]) {
-                rho = p.rho_w;
+                rho = wall_density(p, n);
             } else {
                 C h[Q];
                 if (mask)
@@ -115,7 +115,7 @@ __device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, i
             });
             C Sf[3] = {C(0), C(0), C(0)};
 #pragma unroll
-            for (int a = 0; a < D; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+            for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
             C h[Q];
             if (mask)
                 gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
@@ -281,7 +281,16 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
             if (!m || hipMemcpy(m, p.mask, N, hipMemcpyHostToDevice) != hipSuccess) { free_batch(b); return bfail(nullptr, LBM_E_HIP, "mask upload failed"); }
             cd.mask = m;
         }
+        if (p.rho_wall_field) {   // per-node wall densities of this case
+            void *w = cd.fp64 ? (void *)upload_wall_field<double>(p.rho_wall_field, N)
+                              : (void *)upload_wall_field<float>(p.rho_wall_field, N);
+            if (!w) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "wall density upload failed"); }
+            b->allocs.push_back(w);
+            if (cd.fp64) cd.pd.rho_wf = (const double *)w;
+            else cd.pf.rho_wf = (const float *)w;
+        }
         b->params[c].mask = nullptr;
+        b->params[c].rho_wall_field = nullptr;
         b->ks[c] = kernel_set(cd.D, cd.fp64, cd.mask != nullptr);
         b->nblk[c] = moment_block_count(cd.D, cd.g);
         max_nblk = std::max(max_nblk, b->nblk[c]);

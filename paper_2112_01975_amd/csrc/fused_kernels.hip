@@ -162,11 +162,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         return MASK ? fm.pflags[wrapi(pz, g.nz)] : 0u;
     };
     // rho, s*psi and g_x, g_y of one staged node into ring slot `slot` / g buffer `buf`;
-    // returns g_z. h holds the node's pulled populations, m receives (sum h, j).
-    auto stage = [&](int e, bool solid, const C (&h)[27], C (&m)[4], int slot, int buf) __attribute__((always_inline)) {
+    // returns g_z. h holds the node's pulled populations, m receives (sum h, j); node is
+    // its lattice index (for the wall density of a solid node).
+    auto stage = [&](int e, bool solid, unsigned node, const C (&h)[27], C (&m)[4], int slot, int buf)
+        __attribute__((always_inline)) {
         C rho, ga[3] = {C(0), C(0), C(0)};
         if (MASK && solid) {
-            rho = p.rho_w;
+            rho = wall_density(p, (int)node);
         } else {
             C sum, j[3];
             moments_of<3, C>(h, sum, j);
@@ -202,13 +204,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const uint32_t lm = MM ? links_at(si, zs) : 0u;
         const bool solid = (lm >> LINK_SELF) & 1u;
         if (!solid) pull_all<S, C, MM>(Ab, lm, si, zs, h);
-        const C gzn = stage(e_int, solid, h, m, slot, buf);
+        const C gzn = stage(e_int, solid, (si.v[1][1] + zs[1]) / SB, h, m, slot, buf);
         if (has_halo) {
             C hh[27], mh[4];
             const uint32_t lh = MM ? links_at(sh, zs) : 0u;
             const bool hs = (lh >> LINK_SELF) & 1u;
             if (!hs) pull_all<S, C, MM>(Ab, lh, sh, zs, hh);
-            stage(e_halo, hs, hh, mh, slot, buf);
+            stage(e_halo, hs, (sh.v[1][1] + zs[1]) / SB, hh, mh, slot, buf);
         }
         __syncthreads();
         shift_windows(gzn, buf);
@@ -269,11 +271,11 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 });
             });
 #pragma unroll
-            for (int a = 0; a < 3; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+            for (int a = 0; a < 3; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
         }
         if (halo) {
             C mh[4];
-            stage(e_halo, (lh >> LINK_SELF) & 1u, hh, mh, slot, buf);
+            stage(e_halo, (lh >> LINK_SELF) & 1u, (sh.v[1][1] + zs3[1]) / SB, hh, mh, slot, buf);
         }
 
         // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             pull_all<S, C, MM>(src, l3, si, zs3, qa);
         }
         C gzn = C(0);
-        if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, qa, ma, slot, buf);
+        if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, (si.v[1][1] + zs3[1]) / SB, qa, ma, slot, buf);
         __syncthreads();
         shift_windows(gzn, buf);
     };

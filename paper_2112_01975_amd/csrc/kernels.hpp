@@ -24,6 +24,8 @@ template <class C> struct Params {
     C rho_l, rho_v; // bulk densities of the viscosity interpolation
     int var_visc;
     Eos<C> eos;
+    C accel[3];       // body-force acceleration g: the source gains rho g
+    const C *rho_wf;  // device [N] wall density of each solid node, or nullptr (rho_w)
 };
 
 // number of reduction slots written per workgroup by the moment pass

@@ -30,6 +30,7 @@ struct lbm_ctx {
     uint8_t *mask = nullptr;
     uint32_t *links = nullptr;       // solid-neighbour bits for the fused step (masked only)
     uint32_t *pflags = nullptr;      // per-plane solid flags for the fused step (masked only)
+    void *wall = nullptr;            // per-node wall densities in compute precision (optional)
     double *partials = nullptr, *totals = nullptr;
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
     int nblk = 0;
@@ -64,7 +65,7 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
-    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->partials, c->totals, c->io};
+    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->wall, c->partials, c->totals, c->io};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -126,6 +127,7 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
     c->p = *p;
     c->p.mask = nullptr;
+    c->p.rho_wall_field = nullptr;
     c->D = p->lattice == LBM_D3Q27 ? 3 : 2;
     c->Q = c->D == 3 ? 27 : 9;
     c->fp64 = p->precision == LBM_FP64;
@@ -166,6 +168,16 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         hipMalloc((void **)&c->io, (size_t)(1 + c->D) * N * sizeof(double)) != hipSuccess) {
         free_ctx(c);
         return fail(nullptr, LBM_E_NOMEM, "device allocation failed (" + std::to_string(2 * pop >> 20) + " MiB of populations)");
+    }
+    if (p->rho_wall_field) {   // per-node wall densities (solid entries are the ones used)
+        c->wall = c->fp64 ? (void *)upload_wall_field<double>(p->rho_wall_field, N)
+                          : (void *)upload_wall_field<float>(p->rho_wall_field, N);
+        if (!c->wall) {
+            free_ctx(c);
+            return fail(nullptr, LBM_E_NOMEM, "device allocation of the wall density field failed");
+        }
+        if (c->fp64) c->pd.rho_wf = (const double *)c->wall;
+        else c->pf.rho_wf = (const float *)c->wall;
     }
     if (c->masked) {
         if (hipMalloc((void **)&c->mask, N) != hipSuccess) {

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbm2p.h"
 #include "kernels.hpp"
@@ -50,6 +51,14 @@ inline bool validate_params(const lbm_params *p, std::string *why) {
     if (p->precision != LBM_FP64 && p->precision != LBM_FP32_DEV) { *why = "unknown precision"; return false; }
     if (!isfinite(p->rho_ref) || !isfinite(p->rho_wall)) { *why = "rho_ref and rho_wall must be finite"; return false; }
     if (p->mask && !(p->rho_wall > 0)) { *why = "a mask needs rho_wall > 0"; return false; }
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(p->accel[a])) { *why = "accel must be finite"; return false; }
+    if (p->lattice == LBM_D2Q9 && p->accel[2] != 0.0) { *why = "D2Q9 has no z acceleration"; return false; }
+    if (p->rho_wall_field && p->mask) {
+        const size_t N = (size_t)p->nx * p->ny * p->nz;
+        for (size_t n = 0; n < N; ++n)
+            if (p->mask[n] && !(p->rho_wall_field[n] > 0)) { *why = "rho_wall_field must be > 0 at solid nodes"; return false; }
+    }
     return true;
 }
 
@@ -68,6 +77,22 @@ template <class C> inline void fill_params(const lbm_params *p, Params<C> *q) {
     q->eos.RT = C(p->R * e.T);
     q->eos.aa = C(e.aa);
     q->eos.b = C(p->b);
+    for (int a = 0; a < 3; ++a) q->accel[a] = C(p->accel[a]);
+    q->rho_wf = nullptr;   // set by the caller once the wall field is on the device
+}
+
+// device copy of a per-node wall density field in compute precision C (solid entries
+// used; fluid entries copied as given); nullptr on failure
+template <class C> inline C *upload_wall_field(const double *host, size_t N) {
+    std::vector<C> tmp(N);
+    for (size_t n = 0; n < N; ++n) tmp[n] = C(host[n]);
+    C *d = nullptr;
+    if (hipMalloc((void **)&d, N * sizeof(C)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, tmp.data(), N * sizeof(C), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    return d;
 }
 
 }  // namespace lbm

@@ -15,6 +15,11 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// virtual density of solid node n (Sec. 4.5): per node when a wall field is given
+template <class C> __device__ __forceinline__ C wall_density(const Params<C> &p, int n) {
+    return p.rho_wf ? p.rho_wf[n] : p.rho_w;
+}
+
 template <class C> __device__ __forceinline__ C omega_of(const Params<C> &p, C rho) {
     if (!p.var_visc) return p.omega_l;
     C s = (rho - p.rho_v) / (p.rho_l - p.rho_v);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g
         const int n = x + g.nx * (y + g.ny * z);
         C rho, ga[3] = {C(0), C(0), C(0)};
         if (MASK && mask[n]) {
-            rho = p.rho_w;
+            rho = wall_density(p, n);
         } else {
             Nbr<D> nb(g, x, y, z);
             C h[Lat<D>::Q];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         const int n = x + g.nx * (y + g.ny * z);
         if (MASK && mask[n]) {
             if constexpr (OUT) {
-                out_rho[n] = double(p.rho_w);
+                out_rho[n] = double(wall_density(p, n));
                 for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = 0.0;
             }
             continue;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         });
         C Sf[3] = {C(0), C(0), C(0)};
 #pragma unroll
-        for (int a = 0; a < D; ++a) Sf[a] = -(C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);   // S = -F
+        for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);   // S = -F + rho g
 
         Nbr<D> nb(g, x, y, z);
         C h[Lat<D>::Q];
@@ -224,10 +224,10 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
 // density field of the initial state in compute precision; solid nodes carry rho_w
 template <class C, bool MASK>
 __global__ __launch_bounds__(256) void k_prep_rho(C *__restrict__ rho_f, const double *__restrict__ rho0,
-                                                  const uint8_t *__restrict__ mask, C rho_w, int N) {
+                                                  const uint8_t *__restrict__ mask, Params<C> p, int N) {
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
-    rho_f[n] = (MASK && mask[n]) ? rho_w : C(rho0[n]);
+    rho_f[n] = (MASK && mask[n]) ? wall_density(p, n) : C(rho0[n]);
 }
 
 template <class S> __global__ __launch_bounds__(256) void k_fill_zero(S *__restrict__ A, long long count) {
@@ -272,7 +272,7 @@ template <int D, class S, class C, bool MASK> struct Launch {
                      const double *rho0, const double *U0) {
         const Params<C> &p = *(const Params<C> *)prm;
         hipLaunchKernelGGL((k_prep_rho<C, MASK>), dim3((g.N + 255) / 256), dim3(256), 0, s, (C *)rho, rho0, mask,
-                           p.rho_w, g.N);
+                           p, g.N);
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_INIT>), collide_grid(g), dim3(256), 0, s,
                            (const S *)nullptr, (S *)A, g, mask, p, (const C *)rho, (const C *)nullptr,
                            (double *)nullptr, (double *)U0);

@@ -32,6 +32,8 @@ class Case:
     tau_vapour: float = 0.0
     rho_wall: float = 0.0
     mask: np.ndarray | None = None
+    accel: tuple = (0.0, 0.0, 0.0)
+    rho_wall_field: np.ndarray | None = None
 
     @property
     def N(self):
@@ -46,7 +48,8 @@ class Case:
     def oracle_config(self):
         rv, rl = self.coexistence() if self.eos != T.IDEAL else (1.0, 1.0)
         return O.Config(self.lattice, self.nx, self.ny, self.nz, self.eos, self.a, self.b, 1.0, self.acentric,
-                        self.T_reduced, self.kappa, self.tau, self.tau_vapour, rl, rv, self.rho_wall)
+                        self.T_reduced, self.kappa, self.tau, self.tau_vapour, rl, rv, self.rho_wall,
+                        accel=self.accel, rho_wall_field=self.rho_wall_field)
 
     def params(self, precision=0, rho_ref=0.0, check_every=0):
         import paper_2112_01975_amd as P
@@ -54,7 +57,7 @@ class Case:
         return P.Params(P.LBM_D3Q27 if self.lattice == 3 else P.LBM_D2Q9, self.nx, self.ny, self.nz,
                         EOS_OF[self.eos], self.a, self.b, 1.0, self.acentric, self.T_reduced, self.kappa,
                         self.tau, self.tau_vapour, rl, rv, self.rho_wall, self.mask, precision, rho_ref,
-                        check_every)
+                        check_every, self.accel, self.rho_wall_field)
 
 
 def run_oracle(case: Case, rho0, u0, steps):
@@ -129,7 +132,8 @@ def oracle_one_step_at_nodes(case: Case, pops_bytes, precision, rho_ref, nodes, 
             f[i] = vals + wcl[i] * rho_ref
         cube = Case(D, m, m, m if D == 3 else 1, case.eos, case.a, case.b, case.acentric, case.T_reduced,
                     case.kappa, case.tau, case.tau_vapour, case.rho_wall,
-                    None if mask is None else mask[idx].copy())
+                    None if mask is None else mask[idx].copy(), case.accel,
+                    None if case.rho_wall_field is None else case.rho_wall_field[idx].copy())
         cfg = cube.oracle_config()
         if case.tau_vapour > 0:
             rv, rl = case.coexistence()

@@ -173,3 +173,31 @@ def test_temperature_sweep_64_cases_50000_steps():
             assert abs(vapour / rv - 1) < 1e-1, (i, sc.T_reduced, vapour, rv)
     finally:
         P.lbm_batch_destroy(b)
+
+
+# ------------------------------------------------------------------ layered Poiseuille flow (Sec. 4.2)
+def test_layered_poiseuille_5x200_configuration_a_matches_closed_form():
+    # the paper's grid (5 x 200) and acceleration (1e-8): van der Waals at T/Tc = 0.77
+    # (density ratio 9.98; printed 10.1), mu_l/mu_v = rho_l/rho_v (equal kinematic
+    # viscosity, tau = 1), liquid in the lower half, walls of two solid rows whose virtual
+    # densities are the adjacent phases. From rest to steady state (12 viscous times).
+    import math
+    import paper_2112_01975_amd as P
+    from tests.closed_forms import layered_poiseuille
+    from tests.test_gpu_parity import _layered_channel
+    # FP32 deviation storage runs at g = 1e-6: at 1e-8 the per-step increment rho g w_i of
+    # the liquid populations (~1e-9) is below their FP32 resolution (~1e-7) and most of the
+    # forcing rounds away. The steady Stokes profile is linear in g (u.grad u = 0 here).
+    H, tau = 200, 1.0
+    nu = (tau - 0.5) / 3
+    steps = int(12 * H * H / (math.pi ** 2 * nu))
+    for precision, g in ((0, 1e-8), (1, 1e-6)):
+        case, rho0, (rv, rl) = _layered_channel(2, 5, H, g, tau=tau)
+        with P.Simulation(case.params(precision, rv if precision else 0.0, check_every=-1)) as s:
+            r, U, _ = s.init(rho0).step(steps).moments()
+        ny = H + 4
+        y = np.arange(ny)[2:-2] - 1.5
+        ux = U[0].reshape(ny, 5)[2:-2, 0]
+        ua, _ = layered_poiseuille(y, H, H / 2, g, rl * nu, rv * nu, rl, rv)
+        assert np.abs(ux - ua).max() < 0.02 * ua.max(), (precision, np.abs(ux - ua).max() / ua.max())
+

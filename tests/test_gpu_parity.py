@@ -311,3 +311,72 @@ def test_batched_mixed_lattices_and_masks():
             assert np.abs(Ub - Uo).max() < FP64_U_TOL
     finally:
         P.lbm_batch_destroy(b)
+
+
+# ------------------------------------------------------------------ body force, per-node wall densities
+def _layered_channel(lattice, nx, H, g, tau=1.0, tr=0.77, nz=1):
+    """vdW liquid below / vapour above between two-row walls (normal to y for D2Q9, to z
+    for D3Q27) whose virtual densities match the adjacent phase; gravity along x."""
+    fl0 = T.Fluid(T.VDW, 9 / 49, 2 / 21, tr)
+    a = 9 / 49 * 0.02 / T.kappa_for_width(fl0, 4.0)
+    rv, rl, _ = T.coexistence(T.Fluid(T.VDW, a, 2 / 21, tr))
+    nw = H + 4
+    if lattice == 2:
+        shape, ny = (nw, nx), nw
+        col = np.arange(nw)[:, None] * np.ones((1, nx))
+    else:
+        shape, ny = (nw, nz, nx), nz
+        col = np.arange(nw)[:, None, None] * np.ones((1, nz, nx))
+    mask = ((col < 2) | (col >= nw - 2)).astype(np.uint8).ravel()
+    wall = np.where(col < nw // 2, rl, rv).ravel()
+    rho0 = (0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2 * (col - 1.5 - H / 2) / 4.0)).ravel()
+    if lattice == 2:
+        case = Case(2, nx, nw, 1, eos=T.VDW, a=a, T_reduced=tr, kappa=0.02, tau=tau, rho_wall=rv, mask=mask,
+                    accel=(g, 0.0, 0.0), rho_wall_field=wall)
+    else:   # channel across z: D3Q27 grid (nx, ny = nz_arg, nz = H + 4)
+        case = Case(3, nx, ny, nw, eos=T.VDW, a=a, T_reduced=tr, kappa=0.02, tau=tau, rho_wall=rv, mask=mask,
+                    accel=(g, 0.0, 0.0), rho_wall_field=wall)
+    return case, rho0, (rv, rl)
+
+
+def test_layered_channel_body_force_d2q9_fp64_and_fp32():
+    case, rho0, (rv, rl) = _layered_channel(2, 5, 50, 1e-6)
+    _cmp64(case, rho0, None, 3000)
+    r32, U32, _ = run_gpu(case, rho0, None, 3000, precision=1, rho_ref=rv)
+    r64, U64, _ = run_oracle(case, rho0, None, 3000)
+    fl = ~case.mask.astype(bool)
+    assert max_rel(r32[fl], r64[fl]) < 1e-4
+    assert np.abs(U32 - U64).max() < 1e-3 * np.abs(U64).max()
+
+
+def test_wall_bounded_channel_body_force_d3q27_fused_fp64_and_fp32():
+    # walls across z: the masked fused kernels (plane flags pick the bounce-back planes)
+    case, rho0, (rv, rl) = _layered_channel(3, 70, 36, 1e-6, nz=9)
+    _cmp64(case, rho0, None, 400)
+    r32, U32, _ = run_gpu(case, rho0, None, 400, precision=1, rho_ref=rv)
+    r64, U64, _ = run_oracle(case, rho0, None, 400)
+    fl = ~case.mask.astype(bool)
+    assert max_rel(r32[fl], r64[fl]) < 1e-4
+    assert np.abs(U32 - U64).max() < 2e-3 * np.abs(U64).max()
+
+
+def test_batched_sweep_with_body_force_and_wall_field():
+    # the batch kernel's source and wall densities: a layered channel (D2Q9) and a 3D
+    # wall-bounded channel in one launch, each against the oracle
+    import paper_2112_01975_amd as P
+    c2, r2, _ = _layered_channel(2, 5, 40, 2e-6)
+    c3, r3, _ = _layered_channel(3, 6, 20, 2e-6, nz=5)
+    b = P.lbm_batch_create([c2.params(0), c3.params(0)])
+    try:
+        P.lbm_batch_init_fields(b, 0, r2)
+        P.lbm_batch_init_fields(b, 1, r3)
+        P.lbm_batch_step(b, 300)
+        for i, (c, r0) in enumerate(((c2, r2), (c3, r3))):
+            rb, Ub, _ = P.lbm_batch_moments(b, i, c.N, c.lattice)
+            ro, Uo, _ = run_oracle(c, r0, None, 300)
+            assert max_rel(rb, ro) < FP64_RHO_TOL
+            assert np.abs(Ub - Uo).max() < FP64_U_TOL
+            assert np.abs(Uo[0]).max() > 1e-5        # the body force has driven a flow
+    finally:
+        P.lbm_batch_destroy(b)
+

@@ -29,6 +29,7 @@ from scipy import integrate, optimize
 import pytest
 
 import lbm_inputs as L
+from tests.closed_forms import layered_poiseuille as _layered_u
 from oracle import brute as B
 from oracle import oracle as O
 from oracle import thermo as T
@@ -401,20 +402,6 @@ def test_body_force_poiseuille_single_phase_closed_form(tau, H):
     ua = g * y * (H - y) / (2 * nu) + slip
     assert np.abs(ux - ua[:, None]).max() < 1e-9 * ua.max()
     assert np.abs(U[1]).max() < 1e-15
-
-
-def _layered_u(y, H, h, g, ml, mv, rl, rv):
-    """Steady layered Poiseuille flow (Sec. 4.2, eqs Poiseuille_odes with their boundary
-    conditions; Appendix F): liquid 0 <= y <= h, vapour above. b_l and c_v are the printed
-    coefficients; b_v is the one that solves the printed system (the printed b_v lacks the
-    term -h^2 mu_v rho_l in its numerator)."""
-    al, av = -rl * g / (2 * ml), -rv * g / (2 * mv)
-    den = H * ml - h * ml + h * mv
-    bl = g * (H * H * ml * rv - 2 * h * h * ml * rl + h * h * ml * rv + h * h * mv * rl + 2 * H * h * ml * rl
-              - 2 * H * h * ml * rv) / (2 * ml * den)
-    bv = g * (H * H * ml * rv - h * h * ml * rv - h * h * mv * rl + 2 * h * h * mv * rv) / (2 * mv * den)
-    cv = g * H * (h * h * ml * rv + h * h * mv * rl - 2 * h * h * mv * rv - H * h * ml * rv + H * h * mv * rv) / (2 * mv * den)
-    return np.where(y <= h, al * y * y + bl * y, av * y * y + bv * y + cv), (al, bl, av, bv, cv)
 
 
 def test_layered_poiseuille_coefficients_solve_the_printed_system():
