@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -139,10 +140,23 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     c->ks = kernel_set(c->D, c->fp64, c->masked);
     c->nblk = moment_block_count(c->D, c->g);
     // single-pass z-march for D3Q27 (LBM2P_TWO_PASS=1 forces the two-pass step;
-    // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length)
+    // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length). By default
+    // the z-chunks are as long as possible while every CU still gets a work item: each
+    // chunk re-reads a four-plane z halo and runs a five-plane prologue.
     if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
         const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
-        const int tz = env_int("LBM2P_FUSED_TZ", 128);
+        int cus = 256;
+        {
+            int dev = 0, n = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                cus = n;
+        }
+        const long long tiles = (long long)((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty);
+        long long nzc = (cus + tiles - 1) / tiles;
+        nzc = std::min<long long>(nzc, std::max(1, (c->g.nz + 15) / 16));   // chunks of >= 16 planes
+        nzc = std::max<long long>(nzc, 1);
+        const int tz = env_int("LBM2P_FUSED_TZ", (int)((c->g.nz + nzc - 1) / nzc));
         const unsigned long long bytes = (unsigned long long)c->Q * (unsigned long long)c->g.qs * c->sbytes;
         if (bytes < 0xFFFFFFFFull) {   // one buffer resource addresses the whole lattice
             c->fused = fused_launcher(c->fp64, c->masked, tx, ty);
