@@ -13,7 +13,6 @@ struct FusedGrid {
     int items;             // ntx * nty * nzc work items
     int per_xcd;           // items per XCD (ceil(items / 8))
     int blocks;            // launched workgroups = 8 * per_xcd
-    unsigned pop_bytes;    // Q * qs * sizeof(S): extent of one population lattice (< 4 GiB)
 };
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz);
@@ -33,6 +32,7 @@ using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, 
 void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g);
 
 // nullptr when no fused variant exists for this combination
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty);
+// split: the lattice exceeds one buffer resource (4 GiB) and is addressed as two
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split);
 
 }  // namespace lbm

@@ -47,27 +47,104 @@ struct Stencil {
     unsigned v[3][3];
 };
 
+// One population lattice through one buffer resource (lattices below 4 GiB). Same
+// interface as Lattice2; a bounce-back pull is one load at a per-lane offset.
+template <class S> struct Lattice1 {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned qsb;
+    __device__ __forceinline__ Lattice1(const S *base, long long qs, bool null)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0,
+                                              null ? 0 : (int)(unsigned)(27 * qs * (long long)sizeof(S)), 0x00020000)),
+          qsb((unsigned)(qs * (long long)sizeof(S))) {}
+    template <int i> __device__ __forceinline__ S load(unsigned voff, unsigned soff) const {
+        return raw_load(voff, soff + (unsigned)i * qsb);
+    }
+    // population i from (voff, soff), or population opp(i) of the node itself at (vself,
+    // sself) where solid is set
+    template <int i> __device__ __forceinline__ S load_or_bounce(bool solid, unsigned voff, unsigned soff, unsigned vself,
+                                                               unsigned sself) const {
+        const unsigned off = solid ? vself + sself + (unsigned)opp<3>(i) * qsb : voff + soff + (unsigned)i * qsb;
+        return raw_load(off, 0u);
+    }
+    template <int i> __device__ __forceinline__ void store(unsigned voff, unsigned soff, S v) const {
+        if constexpr (sizeof(S) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff + (unsigned)i * qsb, 0);
+        } else {
+            using u2 = unsigned __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff + (unsigned)i * qsb, 0);
+        }
+    }
+    __device__ __forceinline__ S raw_load(unsigned voff, unsigned soff) const {
+        if constexpr (sizeof(S) == 4) return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        else return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+};
+
+// One population lattice through two buffer resources, populations [0, SPLIT) and
+// [SPLIT, 27): each part stays below the 4 GiB reach of a resource (an FP64 lattice of
+// 33.5 M nodes is 7.2 GB). The population index is a compile-time constant at every
+// access, so the choice of resource costs nothing. voff: per-lane byte offset of the
+// node in its plane; soff: uniform byte offset of the plane. A zero-extent view (null)
+// returns 0 for every load without touching memory.
+template <class S> struct Lattice2 {
+    static constexpr int SPLIT = 14;
+    __amdgpu_buffer_rsrc_t r0, r1;
+    unsigned qsb;   // qs * sizeof(S): bytes between two populations
+    __device__ __forceinline__ Lattice2(const S *base, long long qs, bool null)
+        : r0(__builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0,
+                                               null ? 0 : (int)(unsigned)(SPLIT * qs * (long long)sizeof(S)), 0x00020000)),
+          r1(__builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base) + SPLIT * qs, (short)0,
+                                               null ? 0 : (int)(unsigned)((27 - SPLIT) * qs * (long long)sizeof(S)),
+                                               0x00020000)),
+          qsb((unsigned)(qs * (long long)sizeof(S))) {}
+    template <int i> __device__ __forceinline__ S load(unsigned voff, unsigned soff) const {
+        if constexpr (i < SPLIT) return raw_load(r0, voff, soff + (unsigned)i * qsb);
+        else return raw_load(r1, voff, soff + (unsigned)(i - SPLIT) * qsb);
+    }
+    // i and opp(i) sit in different resources: both are loaded and one is kept
+    template <int i> __device__ __forceinline__ S load_or_bounce(bool solid, unsigned voff, unsigned soff, unsigned vself,
+                                                               unsigned sself) const {
+        const S f = load<i>(voff, soff);
+        const S b = load<opp<3>(i)>(vself, sself);
+        return solid ? b : f;
+    }
+    template <int i> __device__ __forceinline__ void store(unsigned voff, unsigned soff, S v) const {
+        if constexpr (i < SPLIT) raw_store(r0, voff, soff + (unsigned)i * qsb, v);
+        else raw_store(r1, voff, soff + (unsigned)(i - SPLIT) * qsb, v);
+    }
+    static __device__ __forceinline__ S raw_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        if constexpr (sizeof(S) == 4) return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        else return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void raw_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S v) {
+        if constexpr (sizeof(S) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+        } else {
+            using u2 = unsigned __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+        }
+    }
+};
+
 // Solid-neighbour bits of a node (built once per geometry by k_links): bit i is set
 // when the source node r - c_i of population i is solid, bit LINK_SELF when r is.
 constexpr int LINK_SELF = 27;
 
-template <int i, class S, class C, bool MASK>
-__device__ __forceinline__ C pull(const PopBuf<S> &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3]) {
+template <int i, class S, class C, bool MASK, class LT>
+__device__ __forceinline__ C pull(const LT &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3]) {
     constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
     const unsigned vo = st.v[1 - cx][1 - cy];
     if constexpr (MASK && i != 0) {
         // halfway bounce-back: from a solid source node take the opposite population
-        // that this node produced itself
-        const bool solid = (lm >> i) & 1u;
-        const unsigned off = solid ? st.v[1][1] + zs[1] + (unsigned)opp<3>(i) * A.qsb : vo + zs[1 - cz] + (unsigned)i * A.qsb;
-        return C(A.load_at(off, 0u));
+        // that this node produced itself (only planes that touch a solid come here)
+        return C(A.template load_or_bounce<i>((lm >> i) & 1u, vo, zs[1 - cz], st.v[1][1], zs[1]));
     } else {
-        return C(A.load_at(vo, zs[1 - cz] + (unsigned)i * A.qsb));
+        return C(A.template load<i>(vo, zs[1 - cz]));
     }
 }
 
-template <class S, class C, bool MASK>
-__device__ __forceinline__ void pull_all(const PopBuf<S> &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3],
+template <class S, class C, bool MASK, class LT>
+__device__ __forceinline__ void pull_all(const LT &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3],
                                          C (&h)[27]) {
     static_for<0, 27>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -75,7 +152,7 @@ __device__ __forceinline__ void pull_all(const PopBuf<S> &A, uint32_t lm, const 
     });
 }
 
-template <class S, class C, bool MASK, int FTX, int TY, bool REPULL>
+template <class S, class C, bool MASK, int FTX, int TY, bool REPULL, bool SPLIT2>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                       FusedMask fm, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
@@ -97,9 +174,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     const int zc = rest / fg.nty;
     const int x0 = tix * FTX, y0 = tiy * TY, z0 = zc * fg.tz;
 
-    const PopBuf<S> Ab(A, g.qs, fg.pop_bytes), Bb(B, g.qs, fg.pop_bytes);
+    using LT = std::conditional_t<SPLIT2, Lattice2<S>, Lattice1<S>>;   // two resources past 4 GiB
+    const LT Ab(A, g.qs, false), Bb(B, g.qs, false);
     // a zero-extent view of A: loads through it return 0 without touching memory
-    const PopBuf<S> Anull(A, g.qs, 0u);
+    const LT Anull(A, g.qs, true);
     const int t = threadIdx.x;
     const int tx = t & (FTX - 1), ty = t / FTX;
     const int e_int = (ty + 2) * HX + tx + 2;
@@ -280,7 +358,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
 
         // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
         // loads go to Anull
-        const PopBuf<S> src = need3 ? Ab : Anull;
+        const LT src = need3 ? Ab : Anull;
         if (act) {
             constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
             const C drho = ma[0];
@@ -322,7 +400,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                         const C fsd = (Av[2][kz] + Dv[2][kz]) * F + AA * Dv[2][kz];
                         const C hn = om1 * qa[i] + omd * wi + rho * (omega * eqd + fsd);
                         rem -= hn;
-                        Bb.store_at(si.v[1][1], zoff + (unsigned)i * Bb.qsb, S(hn));
+                        Bb.template store<i>(si.v[1][1], zoff, S(hn));
                         qa[i] = pull<i, S, C, MM>(src, l3, si, zs3);
                         // keep the refill load here: left to itself the scheduler sinks all
                         // loads below the last store, and nothing overlaps their latency
@@ -331,7 +409,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 });
             });
             // rest population as the remainder: the per-node mass error stays an unbiased rounding
-            Bb.store_at(si.v[1][1], zoff, S(rem));
+            Bb.template store<0>(si.v[1][1], zoff, S(rem));
             qa[0] = pull<0, S, C, MM>(src, l3, si, zs3);
         } else {
             pull_all<S, C, MM>(src, l3, si, zs3, qa);
@@ -373,10 +451,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     }
 }
 
-template <class S, class C, bool MASK, int TX, int TY, bool REPULL>
+template <class S, class C, bool MASK, int TX, int TY, bool REPULL, bool SPLIT2>
 void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const FusedMask &fm, const void *prm,
                   const FusedGrid &fg) {
-    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
+    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL, SPLIT2>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
                        fm, *(const Params<C> *)prm, fg);
 }
 
@@ -416,16 +494,21 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
 
 namespace {
 template <int TX, int TY> FusedLaunch pick(bool masked) {
-    return masked ? launch_fused<float, float, true, TX, TY, false> : launch_fused<float, float, false, TX, TY, false>;
+    return masked ? launch_fused<float, float, true, TX, TY, false, false>
+                  : launch_fused<float, float, false, TX, TY, false, false>;
 }
 }  // namespace
 
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty) {
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split) {
     if (fp64) {
-        if (tx == 64 && ty == 8)
-            return masked ? launch_fused<double, double, true, 64, 8, true> : launch_fused<double, double, false, 64, 8, true>;
-        return nullptr;
+        if (tx != 64 || ty != 8) return nullptr;
+        if (split)
+            return masked ? launch_fused<double, double, true, 64, 8, true, true>
+                          : launch_fused<double, double, false, 64, 8, true, true>;
+        return masked ? launch_fused<double, double, true, 64, 8, true, false>
+                      : launch_fused<double, double, false, 64, 8, true, false>;
     }
+    if (split) return nullptr;
     if (tx == 64 && ty == 8) return pick<64, 8>(masked);
     if (tx == 32 && ty == 8) return pick<32, 8>(masked);
     if (tx == 32 && ty == 16) return pick<32, 16>(masked);

@@ -157,13 +157,13 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         nzc = std::min<long long>(nzc, std::max(1, (c->g.nz + 15) / 16));   // chunks of >= 16 planes
         nzc = std::max<long long>(nzc, 1);
         const int tz = env_int("LBM2P_FUSED_TZ", (int)((c->g.nz + nzc - 1) / nzc));
-        const unsigned long long bytes = (unsigned long long)c->Q * (unsigned long long)c->g.qs * c->sbytes;
-        if (bytes < 0xFFFFFFFFull) {   // one buffer resource addresses the whole lattice
-            c->fused = fused_launcher(c->fp64, c->masked, tx, ty);
-            if (c->fused) {
-                c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
-                c->fg.pop_bytes = (unsigned)bytes;
-            }
+        // the fused kernel addresses a lattice through one buffer resource, or through two
+        // (populations 0-13 and 14-26) when it exceeds the 4 GiB reach of one
+        const unsigned long long whole = 27ull * (unsigned long long)c->g.qs * c->sbytes;
+        const unsigned long long part = 14ull * (unsigned long long)c->g.qs * c->sbytes;
+        if (part < 0xFFFFFFFFull) {
+            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, whole >= 0xFFFFFFFFull);
+            if (c->fused) c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
         }
     }
     const size_t N = (size_t)c->g.N;
