@@ -94,69 +94,6 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, co
 }
 
 
-// Population array through one buffer resource: 128-bit descriptor in SGPRs, byte offset
-// of the node in a VGPR, byte offset of population i (i * qs * sizeof(S)) as the scalar
-// offset. Hardware range checking returns 0 for reads and drops writes beyond `bytes`.
-// Requires the whole array (Q * qs * sizeof(S)) to be below 4 GiB.
-template <class S> struct PopBuf {
-    __amdgpu_buffer_rsrc_t r;
-    unsigned qsb;   // qs * sizeof(S)
-    __device__ __forceinline__ PopBuf(const S *base, long long qs, unsigned bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0, (int)bytes, 0x00020000)),
-          qsb((unsigned)(qs * (long long)sizeof(S))) {}
-    __device__ __forceinline__ S load(int i, unsigned node) const;
-    __device__ __forceinline__ void store(int i, unsigned node, S v) const;
-    // explicit byte offsets: voff per lane, soff uniform
-    __device__ __forceinline__ S load_at(unsigned voff, unsigned soff) const;
-    __device__ __forceinline__ void store_at(unsigned voff, unsigned soff, S v) const;
-};
-template <> __device__ __forceinline__ float PopBuf<float>::load(int i, unsigned node) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, node * 4u, (unsigned)i * qsb, 0));
-}
-template <> __device__ __forceinline__ void PopBuf<float>::store(int i, unsigned node, float v) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, node * 4u, (unsigned)i * qsb, 0);
-}
-template <> __device__ __forceinline__ float PopBuf<float>::load_at(unsigned voff, unsigned soff) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ void PopBuf<float>::store_at(unsigned voff, unsigned soff, float v) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-}
-template <> __device__ __forceinline__ double PopBuf<double>::load_at(unsigned voff, unsigned soff) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ void PopBuf<double>::store_at(unsigned voff, unsigned soff, double v) const {
-    using u2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
-}
-template <> __device__ __forceinline__ double PopBuf<double>::load(int i, unsigned node) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, node * 8u, (unsigned)i * qsb, 0));
-}
-template <> __device__ __forceinline__ void PopBuf<double>::store(int i, unsigned node, double v) const {
-    using u2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, node * 8u, (unsigned)i * qsb, 0);
-}
-
-// pull gather through a buffer resource (same semantics as gather())
-template <int D, class S, class C, bool MASK>
-__device__ __forceinline__ void gather_buf(const PopBuf<S> &A, const uint8_t *__restrict__ mask, const Nbr<D> &nb,
-                                           int n, C (&h)[Lat<D>::Q]) {
-    static_for<0, Lat<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
-        if constexpr (i == 0) {
-            h[0] = C(A.load(0, (unsigned)n));
-        } else {
-            const unsigned s = (unsigned)nb.at(-cx, -cy, -cz);
-            if constexpr (MASK) {
-                h[i] = ld_at(mask, s) ? C(A.load(opp<D>(i), (unsigned)n)) : C(A.load(i, s));
-            } else {
-                h[i] = C(A.load(i, s));
-            }
-        }
-    });
-}
-
 // sum h and j = sum c h in a fixed order (pass 1 and pass 2 must agree bit for bit)
 template <int D, class C>
 __device__ __forceinline__ void moments_of(const C (&h)[Lat<D>::Q], C &sum, C (&j)[3]) {
