@@ -252,6 +252,26 @@ def test_fused_step_matches_two_pass_fp32(dims, masked, monkeypatch):
     assert np.abs(fused[1] - two[1]).max() < 1e-6
 
 
+@pytest.mark.parametrize("dims,masked", [((70, 36, 40), False), ((5, 3, 7), False), ((48, 20, 36), True)])
+def test_fused_step_matches_two_pass_fp64(dims, masked, monkeypatch):
+    # the FP64 z-march (queued moments, collided plane pulled again) against the two-pass
+    # step on ragged tiles, several z-chunks, tiny grids and a solid mask: same arithmetic
+    # up to the order of a few sums, so agreement to rounding
+    nx, ny, nz = dims
+    mask = L.pillar_mask(nx, ny, nz, 4, 4, 5) if masked else None
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6,
+                rho_wall=0.0102306 if masked else 0.0, mask=mask, tau_vapour=1.25 if masked else 0.0)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(nx, ny, nz, min(nx, ny, nz) / 4, rl, rv, 5.0, noise=1e-5, seed=1007)
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "16")
+    fused = run_gpu(case, rho0, None, 30)
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    two = run_gpu(case, rho0, None, 30)
+    assert max_rel(fused[0], two[0]) < 1e-12
+    assert np.abs(fused[1] - two[1]).max() < 1e-13
+    assert abs(fused[2][0] / two[2][0] - 1) < 1e-14
+
+
 # ---------------------------------------------------------------- batched sweep
 def _sweep_cases(n, steps_len_lo=32, steps_len_hi=96):
     """A reduced temperature sweep: D2Q9 4 x L flat interfaces, FP64 from T/Tc >= 0.95."""
