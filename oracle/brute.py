@@ -8,7 +8,9 @@ The equation of state comes from thermo.Fluid.
 
 Step, with the readings used throughout the oracle: S = -F for the discrete
 Korteweg force of eq Kforce_final, xi* = u + S/rho, zeta* = 1/3 + xi*^2 + Phi/rho,
-Phi = (1 - omega/2) d_a(rho u_a^3) by central differences, halfway bounce-back.
+Phi = (1 - omega/2) d_a(rho u_a^3) by central differences, halfway bounce-back,
+or, when per-link wall distances are given, linearly interpolated bounce-back
+(Bouzidi et al., the wall scheme cited in Sec. 4.5).
 """
 from __future__ import annotations
 
@@ -49,7 +51,8 @@ class BruteForce:
     """Tiny-grid FP64 reference: state f[(c)] on a grid of shape (ny, nx) or (nz, ny, nx)."""
 
     def __init__(self, D, shape, fluid: Fluid, kappa, tau, rho_wall=0.0, mask=None,
-                 tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0, accel=(0.0, 0.0, 0.0), rho_wall_field=None):
+                 tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0, accel=(0.0, 0.0, 0.0), rho_wall_field=None,
+                 link_q=None):
         self.D, self.shape = D, tuple(shape)
         self.fluid, self.kappa = fluid, kappa
         self.tau, self.tau_v, self.rl, self.rv = tau, tau_vapour, rho_liquid, rho_vapour
@@ -57,6 +60,9 @@ class BruteForce:
         self.rho_wall = rho_wall if rho_wall_field is None else np.asarray(rho_wall_field, float).reshape(shape)
         self.accel = [float(g) for g in accel][:D]      # body-force acceleration: source + rho g
         self.solid = np.zeros(self.shape, bool) if mask is None else mask.reshape(self.shape).astype(bool)
+        # link_q[(c)][r]: fraction of the link r -> r + c cut off by the wall (only links
+        # from fluid into solid nodes matter); None means 1/2 everywhere
+        self.link_q = None if link_q is None else np.asarray(link_q, float).reshape((3,) * D + self.shape)
         self.vel = _velocities(D)
         self.wcube = AXIS_W
         for _ in range(D - 1):
@@ -137,7 +143,16 @@ class BruteForce:
                 ib = self._idx(tuple(-ci for ci in c))
                 arrived = _roll(fpost[i], c, -1)            # value from r - c
                 src_solid = _roll(self.solid, c, -1)
-                fnew[i] = np.where(src_solid, fpost[ib], arrived)
+                back = fpost[ib]                            # halfway: reflected at r itself
+                if self.link_q is not None:
+                    # the wall cuts r -> r - c at q; pull back the value the interpolation
+                    # places at r: from r and r + c (q < 1/2), or from both directions at r
+                    q = self.link_q[ib]
+                    behind = np.where(_roll(self.solid, c, 1), fpost[ib], _roll(fpost[ib], c, 1))
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        back = np.where(q < 0.5, 2.0 * q * fpost[ib] + (1.0 - 2.0 * q) * behind,
+                                        fpost[ib] / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fpost[i])
+                fnew[i] = np.where(src_solid, back, arrived)
             fnew[(slice(None),) * D + (self.solid,)] = 0.0
             self.f = fnew
         return self

@@ -26,7 +26,9 @@
  *      that makes f* the equilibrium at the incremented velocity when Phi = 0);
  *   7. LBGK update f + omega (f_eq - f) + (f* - f_eq) (eq LBGK) and streaming to
  *      r + c_i; a link whose target is solid is reflected back into the opposite
- *      population of its own node (halfway bounce-back).
+ *      population of its own node (halfway bounce-back), or, with per-link wall
+ *      distances, by the linearly interpolated bounce-back of Bouzidi et al. that the
+ *      paper uses for curved walls (Sec. 4.5, Sec. 5.3).
  * Output velocity U = u + S/(2 rho) (Sec. 2.3.5, Appendix D).
  */
 #include <math.h>
@@ -49,6 +51,10 @@ typedef struct {
                                8 initial velocity taken as the bare u */
     double accel[3];        /* body-force acceleration g: the source gains rho g (Sec. 4.2) */
     const double *rho_wall_field; /* NULL or [N]: wall density of each solid node (copied) */
+    const double *link_q;   /* NULL or [Q][N] in this oracle's population order: for a fluid
+                               node n whose link n -> n + c_i ends in a solid node, the wall's
+                               fractional distance q in (0, 1] along that link (interpolated
+                               bounce-back, Sec. 4.5); NULL = halfway, q = 1/2 (copied) */
 } orc_params;
 
 typedef struct {
@@ -61,6 +67,7 @@ typedef struct {
     double T, aalpha;
     unsigned char *mask;    /* NULL = fully periodic */
     double *rho_wf;         /* NULL or [N]: per-node wall density */
+    double *lq, *fpost;     /* interpolated bounce-back: [Q][N] link distances, post-collision */
     double *f, *fn;         /* [Q][N], pre-collision populations at time t */
     double *rho, *u, *psi, *sgn, *g, *S; /* u, g, S: [3][N] */
 } orc_ctx;
@@ -204,7 +211,7 @@ void orc_destroy(void *h)
     orc_ctx *x = (orc_ctx *)h;
     if (!x) return;
     free(x->mask); free(x->f); free(x->fn); free(x->rho); free(x->u);
-    free(x->psi); free(x->sgn); free(x->g); free(x->S); free(x->rho_wf);
+    free(x->psi); free(x->sgn); free(x->g); free(x->S); free(x->rho_wf); free(x->lq); free(x->fpost);
     free(x);
 }
 
@@ -239,6 +246,13 @@ void *orc_create(const orc_params *p, const unsigned char *mask)
         memcpy(x->mask, mask, N);
     }
     x->p.rho_wall_field = NULL;
+    x->p.link_q = NULL;
+    if (p->link_q) {
+        x->lq = (double *)malloc((size_t)x->Q * N * sizeof(double));
+        x->fpost = (double *)malloc((size_t)x->Q * N * sizeof(double));
+        if (!x->lq || !x->fpost) { orc_destroy(x); return NULL; }
+        memcpy(x->lq, p->link_q, (size_t)x->Q * N * sizeof(double));
+    }
     if (p->rho_wall_field) {
         x->rho_wf = (double *)malloc(N * sizeof(double));
         if (!x->rho_wf) { orc_destroy(x); return NULL; }
@@ -379,29 +393,85 @@ void orc_collide(const void *h, const double *f, const double *S, const double *
     collide_node((const orc_ctx *)h, f, S, Phi, omega, out);
 }
 
+/* post-collision populations of fluid node n (steps 5-6) into fp */
+static void collide_at(orc_ctx *x, long n, double *fp)
+{
+    long N = x->N;
+    int D = x->D, Q = x->Q;
+    double f[27], S[3], Phi[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) f[i] = x->f[i * N + n];
+    double omega = omega_at(x, x->rho[n]);
+    for (int a = 0; a < 3; ++a) S[a] = x->S[a * N + n];
+    if (!(x->p.variant & 4))
+        for (int a = 0; a < D; ++a) {
+            int e[3] = {0, 0, 0};
+            e[a] = 1;
+            long np = nbr(x, n, 1, e), nm = nbr(x, n, -1, e);
+            Phi[a] = (1.0 - 0.5 * omega) * 0.5 * (x->g[a * N + np] - x->g[a * N + nm]);
+        }
+    collide_node(x, f, S, Phi, omega, fp);
+}
+
+/* One step with interpolated bounce-back (Bouzidi et al., the scheme the paper cites for
+ * walls, Sec. 4.5): every fluid node is collided first; then each post-collision
+ * population streams to n + c_i, or, when that node is solid and the wall cuts the link
+ * at fraction q, returns to n as the opposite population, linearly interpolated:
+ *   q <  1/2: 2q fp_i(n) + (1 - 2q) fp_i(n - c_i)   (fp_i(n) if n - c_i is solid)
+ *   q >= 1/2: fp_i(n)/(2q) + (1 - 1/(2q)) fp_opp(i)(n)
+ * q = 1/2 is halfway bounce-back. */
+static void step_interpolated(orc_ctx *x)
+{
+    long N = x->N;
+    int Q = x->Q;
+    fields(x);
+    memset(x->fn, 0, sizeof(double) * (size_t)Q * N);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        if (solid(x, n)) continue;
+        double fp[27];
+        collide_at(x, n, fp);
+        for (int i = 0; i < Q; ++i) x->fpost[i * N + n] = fp[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        if (solid(x, n)) continue;
+        for (int i = 0; i < Q; ++i) {
+            long d = nbr(x, n, 1, x->c[i]);
+            double v = x->fpost[i * N + n];
+            if (!solid(x, d)) {
+                x->fn[i * N + d] = v;
+                continue;
+            }
+            double q = x->lq[i * N + n], r;
+            if (q < 0.5) {
+                long b = nbr(x, n, -1, x->c[i]);
+                r = solid(x, b) ? v : 2.0 * q * v + (1.0 - 2.0 * q) * x->fpost[i * N + b];
+            } else {
+                r = v / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * x->fpost[x->opp[i] * N + n];
+            }
+            x->fn[x->opp[i] * N + n] = r;
+        }
+    }
+    double *tmp = x->f; x->f = x->fn; x->fn = tmp;
+}
+
 void orc_step(void *h, long steps)
 {
     orc_ctx *x = (orc_ctx *)h;
     long N = x->N;
-    int D = x->D, Q = x->Q;
+    int Q = x->Q;
+    if (x->lq) {
+        for (long t = 0; t < steps; ++t) step_interpolated(x);
+        return;
+    }
     for (long t = 0; t < steps; ++t) {
         fields(x);
         memset(x->fn, 0, sizeof(double) * (size_t)Q * N);
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; ++n) {
             if (solid(x, n)) continue;
-            double f[27], fp[27], S[3], Phi[3] = {0, 0, 0};
-            for (int i = 0; i < Q; ++i) f[i] = x->f[i * N + n];
-            double omega = omega_at(x, x->rho[n]);
-            for (int a = 0; a < 3; ++a) S[a] = x->S[a * N + n];
-            if (!(x->p.variant & 4))
-                for (int a = 0; a < D; ++a) {
-                    int e[3] = {0, 0, 0};
-                    e[a] = 1;
-                    long np = nbr(x, n, 1, e), nm = nbr(x, n, -1, e);
-                    Phi[a] = (1.0 - 0.5 * omega) * 0.5 * (x->g[a * N + np] - x->g[a * N + nm]);
-                }
-            collide_node(x, f, S, Phi, omega, fp);
+            double fp[27];
+            collide_at(x, n, fp);
             for (int i = 0; i < Q; ++i) {
                 long d = nbr(x, n, 1, x->c[i]);
                 if (solid(x, d))

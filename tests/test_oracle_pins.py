@@ -464,6 +464,107 @@ def test_oracle_matches_numpy_step_with_body_force_and_wall_field(D):
     assert np.abs(U1 - U2).max() < 1e-13
 
 
+def _frac_channel(D, nf, qb, qt, tau, g=1e-6, interpolated=True, nx=4, nz=3):
+    """Gravity-driven ideal-gas channel: nf fluid rows between one solid row at each end,
+    the walls cutting the links from the first and last fluid rows at qb and qt (flat
+    walls: every link into a wall is cut at the same fraction). Returns the steady x
+    velocity at the fluid rows, their distance from the bottom wall, and the width."""
+    ny = nf + 2
+    nz = nz if D == 3 else 1
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0] = 1
+    mask[:, -1] = 1
+    lq = np.zeros((3,) * D + (nz, ny, nx))
+    lq[:, 0, ..., 1, :] = qb          # links with c_y = -1 from row 1
+    lq[:, 2, ..., ny - 2, :] = qt     # links with c_y = +1 from row ny - 2
+    H = (nf - 1) + qb + qt
+    cfg = O.Config(D, nx, ny, nz, T.IDEAL, 0.0, 0.0, 1.0, 0.0, 1.0, 0.0, tau, rho_wall=1.0,
+                   accel=(g, 0.0, 0.0), link_q=lq.reshape((3,) * D + (-1,)) if interpolated else None)
+    nu = (tau - 0.5) / 3
+    steps = int(30 * H * H / (math.pi ** 2 * nu))
+    _, U, _ = O.Oracle(cfg, mask.ravel()).init(np.ones(nx * ny * nz)).step(steps).moments()
+    ux = U[0].reshape(nz, ny, nx)[:, 1:-1]
+    assert np.abs(ux - ux[:1, :, :1]).max() < 1e-12 * ux.max()      # uniform along x and z
+    return ux[0, :, 0], np.arange(nf) + qb, H, g / (2 * nu)
+
+
+def _wall_offsets(u, y, H, k):
+    """Fit u = -k y^2 + b y + c (the curvature fixed by the momentum balance); return the
+    fitted zeros' offsets from the true walls at 0 and H, and the fit's worst residual."""
+    A = np.stack([y, np.ones_like(y)], 1)
+    b, c = np.linalg.lstsq(A, u + k * y * y, rcond=None)[0]
+    lo, hi = sorted(np.roots([-k, b, c]))
+    return lo, hi - H, np.abs(A @ [b, c] - k * y * y - u).max() / u.max()
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_interpolated_bounce_back_at_half_is_halfway(D):
+    # q = 1/2 everywhere: the interpolation weights are 1 and 0, so the step is halfway
+    # bounce-back bit for bit (two-phase state, random solids)
+    nz, ny, nx = (1, 9, 8) if D == 2 else (5, 6, 7)
+    N = nx * ny * nz
+    rv, rl, _ = T.coexistence(T.Fluid(T.VDW, 0.02, B21, 0.7))
+    rho, u = L.random_state(N, D, rv, rl, 0.05, 31)
+    mask = L.random_mask(nx, ny, nz, 0.2, 5)
+    half = np.full((3,) * D + (N,), 0.5)
+    out = []
+    for lq in (None, half):
+        cfg = O.Config(D, nx, ny, nz, T.VDW, 0.02, B21, 1.0, 0.0, 0.7, 0.02, 0.8, rho_wall=rv, link_q=lq)
+        out.append(O.Oracle(cfg, mask).init(rho, u).step(8).moments())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_oracle_matches_numpy_step_with_interpolated_walls(D):
+    nz, ny, nx = (1, 8, 7) if D == 2 else (4, 6, 5)
+    N = nx * ny * nz
+    fl = T.Fluid(T.VDW, 0.02, B21, 0.7)
+    rv, rl, _ = T.coexistence(fl)
+    rho, u = L.random_state(N, D, rv, rl, 0.05, 14)
+    mask = L.random_mask(nx, ny, nz, 0.2, 6)
+    lq = np.random.default_rng(8).uniform(0.05, 1.0, (3,) * D + (N,))   # both branches
+    cfg = O.Config(D, nx, ny, nz, T.VDW, 0.02, B21, 1.0, 0.0, 0.7, 0.02, 0.8, rho_wall=rv, link_q=lq)
+    r1, U1, _ = O.Oracle(cfg, mask).init(rho, u).step(10).moments()
+    shape = (ny, nx) if D == 2 else (nz, ny, nx)
+    bf = B.BruteForce(D, shape, fl, 0.02, 0.8, rho_wall=rv, mask=mask, link_q=lq)
+    r2, U2 = bf.init(rho, u).step(10).moments()
+    assert np.abs(r1 - r2).max() < 1e-13 * np.abs(r2).max()
+    assert np.abs(U1 - U2).max() < 1e-13
+
+
+@pytest.mark.parametrize("tau,qb,qt", [(0.8, 0.25, 0.75), (0.8, 0.1, 0.9), (0.5 + math.sqrt(3) / 4, 0.4, 0.3),
+                                       (1.2, 0.25, 0.75), (1.2, 0.6, 0.95)])
+def test_interpolated_walls_poiseuille_second_order(tau, qb, qt):
+    # Between walls at fractional link positions the steady state is a parabola with the
+    # curvature g / (2 nu) of the momentum balance, and its zeros converge to the true wall
+    # positions at second order: the offsets halve, and the relative velocity error falls
+    # four-fold, when the width doubles. Halfway bounce-back on the same rows sees walls
+    # midway along the links and misses by |q - 1/2| at any width.
+    res = {}
+    for nf in (16, 32):
+        u, y, H, k = _frac_channel(2, nf, qb, qt, tau)
+        lo, hi, fit = _wall_offsets(u, y, H, k)
+        assert fit < 1e-9
+        err = np.abs(u - k * y * (H - y)).max() / u.max()
+        res[nf] = (lo, hi, err)
+    assert max(abs(res[16][0]), abs(res[16][1])) < 0.1
+    for j in (0, 1):
+        assert abs(res[32][j]) <= 0.55 * abs(res[16][j]) + 1e-6
+    assert 3.5 < res[16][2] / res[32][2] < 4.5
+    u, y, H, k = _frac_channel(2, 16, qb, qt, tau, interpolated=False)
+    lo, hi, _ = _wall_offsets(u, y, H, k)
+    assert abs(lo + (0.5 - qb)) < 0.1 and abs(hi - (0.5 - qt)) < 0.1
+
+
+def test_interpolated_walls_poiseuille_d3q27():
+    # the same channel on D3Q27, whose diagonal links cross the walls at the same fraction
+    u, y, H, k = _frac_channel(3, 16, 0.3, 0.8, 0.8)
+    u2, _, _, _ = _frac_channel(2, 16, 0.3, 0.8, 0.8)
+    lo, hi, fit = _wall_offsets(u, y, H, k)
+    assert fit < 1e-9 and max(abs(lo), abs(hi)) < 0.1
+    assert np.abs(u - u2).max() < 0.01 * u2.max()
+
+
 # ------------------------------------------------------------------ physics
 def _flat_errors(a, tr=0.8, kappa=0.02, steps=12000, variant=0):
     fl = T.Fluid(T.VDW, a, B21, tr)
