@@ -84,6 +84,18 @@ typedef struct {
                                node (> 0 where mask is set), replacing rho_wall, so that
                                walls of different wettability or walls touching different
                                phases can coexist; copied at create */
+    const double *link_q;   /* nullable host array [Q][N] in lbm_velocities order: for a
+                               fluid node n whose neighbour n + c_j is solid, entry (j, n)
+                               is the fraction q in (0, 1] of the link from n to n + c_j
+                               at which the wall lies; other entries are ignored. Walls
+                               then use the linearly interpolated bounce-back of Bouzidi
+                               et al. that the paper applies to curved walls (Sec. 4.5,
+                               Sec. 5.3) instead of halfway bounce-back (q = 1/2 gives the
+                               same step). Needs a mask; a node cut on two opposite links
+                               with q, q' >= 1/2 needs 1/(2q) + 1/(2q') >= 1.01 (the
+                               initial state is otherwise not representable). Such
+                               contexts take the two-pass step; lbm_batch_create rejects
+                               it. Copied at create */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -104,7 +116,7 @@ int lbm_create(const lbm_params *p, lbm_ctx **out);
 int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u);
 
 /* Advances n time steps of eq LBGK (stream-collide with the Korteweg force and
- * halfway bounce-back at solid nodes). Runs the FP64 watchdog as selected by
+ * halfway, or with link_q interpolated, bounce-back at solid nodes). Runs the FP64 watchdog as selected by
  * check_every; returns LBM_E_DIVERGED / LBM_E_DOMAIN when it trips. When no
  * check runs, the call only enqueues work on the context stream. */
 int lbm_step(lbm_ctx *c, int64_t n);
@@ -141,7 +153,8 @@ int lbm_set_populations(lbm_ctx *c, const void *host);
  * or LBM_E_INVAL. Together with lbm_get_populations this documents the checkpoint
  * layout: population i of node n is the post-collision value that node n produced,
  * so the pre-collision f_i(r) is entry i at r - c_i (entry opp(i) at r when r - c_i is
- * solid); FP32 storage holds f_i - w_i rho_ref. */
+ * solid; with link_q, the interpolation of entries opp(i) at r and r + c_i, or opp(i)
+ * and i at r, that the link's q selects); FP32 storage holds f_i - w_i rho_ref. */
 int lbm_velocities(int lattice, int *c);
 
 /* Runs n steps with HIP events around every kernel launch on the context

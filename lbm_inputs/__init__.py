@@ -14,6 +14,7 @@ draw n of stream `seed` is mix(seed + (n + 1) * gamma), gamma = 0x9E3779B97F4A7C
 """
 from __future__ import annotations
 
+import itertools
 from dataclasses import dataclass
 
 import numpy as np
@@ -116,6 +117,45 @@ def random_mask(nx: int, ny: int, nz: int, fraction: float, seed: int) -> np.nda
     """Sparse random solid nodes (for bounce-back parity on tiny grids)."""
     u = (splitmix64(seed, nx * ny * nz) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
     return (u < fraction).astype(np.uint8)
+
+
+def random_link_q(D: int, N: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """Wall fractions uniform in [lo, hi) for every link of every node, shape (3,)*D + (N,):
+    entry [c + 1][n] belongs to the link n -> n + c (only links into solid nodes matter)."""
+    u = (splitmix64(seed, 3 ** D * N) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (lo + (hi - lo) * u).reshape((3,) * D + (N,))
+
+
+def sphere_obstacle(nx: int, ny: int, nz: int, centre, radius: float):
+    """Solid ball (disc when nz = 1 and len(centre) = 2) of the given radius around
+    centre, which must lie at least radius + 1 from every face (no periodic images).
+
+    Returns (mask uint8 [N], link_q (3,)*D + (N,)): for a fluid node p and a link c whose
+    end p + c is solid, link_q[c + 1][p] is the fraction q in (0, 1] at which the segment
+    p -> p + c meets the sphere, the smaller root of |p + q c - centre| = radius.
+    """
+    D = len(centre)
+    x, y, z = _grid(nx, ny, nz)
+    pos = np.stack([x, y, z][:D]).astype(np.float64)
+    s = np.asarray(centre, dtype=np.float64).reshape(D, 1)
+    d = pos - s
+    solid = (d * d).sum(0) <= radius * radius
+    N = nx * ny * nz
+    lq = np.zeros((3,) * D + (N,))
+    for c in itertools.product((-1, 0, 1), repeat=D):
+        if not any(c):
+            continue
+        cv = np.asarray(c, dtype=np.float64).reshape(D, 1)
+        idx = [x.astype(np.int64), y.astype(np.int64), z.astype(np.int64)][:D]
+        tgt = [(idx[a] + c[a]) % (nx, ny, nz)[a] for a in range(D)]
+        flat = tgt[0] + nx * (tgt[1] + (ny * tgt[2] if D == 3 else 0))
+        end = solid[flat] & ~solid
+        cc = float((cv * cv).sum())
+        dc = (d * cv).sum(0)
+        disc = np.maximum(dc * dc - cc * ((d * d).sum(0) - radius * radius), 0.0)
+        q = (-dc - np.sqrt(disc)) / cc
+        lq[tuple(ci + 1 for ci in c)] = np.where(end, np.clip(q, 1e-6, 1.0), 0.0)
+    return solid.astype(np.uint8), lq
 
 
 def random_state(N: int, D: int, rho_lo: float, rho_hi: float, umax: float, seed: int):

@@ -243,6 +243,8 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
     for (int c = 0; c < ncases; ++c) {
         std::string why;
         if (!validate_params(&cases[c], &why)) return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": " + why);
+        if (cases[c].link_q)
+            return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": link_q (interpolated bounce-back) is not supported by the batch");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch;
     if (!b) return bfail(nullptr, LBM_E_NOMEM, "host allocation failed");

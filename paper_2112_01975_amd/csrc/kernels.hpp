@@ -26,6 +26,7 @@ template <class C> struct Params {
     Eos<C> eos;
     C accel[3];       // body-force acceleration g: the source gains rho g
     const C *rho_wf;  // device [N] wall density of each solid node, or nullptr (rho_w)
+    const C *link_q;  // device [Q][qs] wall fraction of the link n -> n + c_j, or nullptr (halfway)
 };
 
 // number of reduction slots written per workgroup by the moment pass
@@ -37,6 +38,8 @@ struct KernelSet {
     void (*fill_zero)(hipStream_t, void *A, long long count);
     // f = f_eq(rho0, u) with u = U0 - S/(2 rho0), written in pull layout with bounce-back
     // links folded in; rho is the compute-precision density scratch field
+    // populations folded for halfway bounce-back; with link_q the wall slots are then
+    // re-solved so that the interpolated pull returns the same equilibria
     void (*init)(hipStream_t, void *A, const Geom &, const uint8_t *mask, const void *params, void *rho,
                  const double *rho0, const double *U0);
     // rho and g = rho u^3 of the current state, per-workgroup FP64 partials

@@ -32,6 +32,7 @@ struct lbm_ctx {
     uint32_t *links = nullptr;       // solid-neighbour bits for the fused step (masked only)
     uint32_t *pflags = nullptr;      // per-plane solid flags for the fused step (masked only)
     void *wall = nullptr;            // per-node wall densities in compute precision (optional)
+    void *lq = nullptr;              // per-link wall fractions in compute precision (optional)
     double *partials = nullptr, *totals = nullptr;
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
     int nblk = 0;
@@ -66,7 +67,7 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
-    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->wall, c->partials, c->totals, c->io};
+    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->wall, c->lq, c->partials, c->totals, c->io};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -129,6 +130,7 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     c->p = *p;
     c->p.mask = nullptr;
     c->p.rho_wall_field = nullptr;
+    c->p.link_q = nullptr;
     c->D = p->lattice == LBM_D3Q27 ? 3 : 2;
     c->Q = c->D == 3 ? 27 : 9;
     c->fp64 = p->precision == LBM_FP64;
@@ -142,8 +144,9 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     // single-pass z-march for D3Q27 (LBM2P_TWO_PASS=1 forces the two-pass step;
     // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length). By default
     // the z-chunks are as long as possible while every CU still gets a work item: each
-    // chunk re-reads a four-plane z halo and runs a five-plane prologue.
-    if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
+    // chunk re-reads a four-plane z halo and runs a five-plane prologue. Interpolated
+    // bounce-back (link_q) runs in the two-pass step only.
+    if (c->D == 3 && !p->link_q && !env_int("LBM2P_TWO_PASS", 0)) {
         const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
         int cus = 256;
         {
@@ -192,6 +195,16 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         }
         if (c->fp64) c->pd.rho_wf = (const double *)c->wall;
         else c->pf.rho_wf = (const float *)c->wall;
+    }
+    if (p->link_q) {   // wall fractions of the links into solid nodes
+        c->lq = c->fp64 ? (void *)upload_link_q<double>(p->link_q, c->Q, N, c->g.qs)
+                        : (void *)upload_link_q<float>(p->link_q, c->Q, N, c->g.qs);
+        if (!c->lq) {
+            free_ctx(c);
+            return fail(nullptr, LBM_E_NOMEM, "device allocation of the link fractions failed");
+        }
+        if (c->fp64) c->pd.link_q = (const double *)c->lq;
+        else c->pf.link_q = (const float *)c->lq;
     }
     if (c->masked) {
         if (hipMalloc((void **)&c->mask, N) != hipSuccess) {

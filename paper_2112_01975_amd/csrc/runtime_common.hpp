@@ -24,6 +24,45 @@ inline Geom make_geom(int nx, int ny, int nz) {
     return g;
 }
 
+// Wall fractions of every link from a fluid node into a solid one must lie in (0, 1]; a
+// node cut on both links of one axis pair with q, q' >= 1/2 needs 1/(2q) + 1/(2q') - 1 >=
+// 0.01, the determinant of the 2x2 system that places its initial populations.
+inline bool check_link_q(const lbm_params *p, std::string *why) {
+    const int D = p->lattice == LBM_D3Q27 ? 3 : 2, Q = D == 3 ? 27 : 9;
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const size_t N = (size_t)nx * ny * nz;
+    int c[27][3];
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) c[i][a] = D == 3 ? Lat<3>::c(i, a) : Lat<2>::c(i, a);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = (size_t)x + nx * ((size_t)y + (size_t)ny * z);
+                if (p->mask[n]) continue;
+                double qs[27];
+                for (int i = 1; i < Q; ++i) {
+                    const size_t d = (size_t)((x + c[i][0] + nx) % nx) +
+                                     nx * ((size_t)((y + c[i][1] + ny) % ny) + (size_t)ny * ((z + c[i][2] + nz) % nz));
+                    qs[i] = -1.0;
+                    if (!p->mask[d]) continue;
+                    const double q = p->link_q[(size_t)i * N + n];
+                    if (!(q > 0.0 && q <= 1.0)) {
+                        *why = "link_q must lie in (0, 1] on every link from a fluid into a solid node";
+                        return false;
+                    }
+                    qs[i] = q;
+                }
+                for (int i = 1; i < Q; ++i) {
+                    const int j = D == 3 ? opp<3>(i) : opp<2>(i);
+                    if (qs[i] >= 0.5 && qs[j] >= 0.5 && 0.5 / qs[i] + 0.5 / qs[j] - 1.0 < 0.01) {
+                        *why = "link_q: a node cut on two opposite links with q, q' >= 1/2 needs 1/(2q) + 1/(2q') >= 1.01";
+                        return false;
+                    }
+                }
+            }
+    return true;
+}
+
 inline bool validate_params(const lbm_params *p, std::string *why) {
     if (!p) { *why = "params is NULL"; return false; }
     if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27) { *why = "lattice must be LBM_D2Q9 or LBM_D3Q27"; return false; }
@@ -59,6 +98,10 @@ inline bool validate_params(const lbm_params *p, std::string *why) {
         for (size_t n = 0; n < N; ++n)
             if (p->mask[n] && !(p->rho_wall_field[n] > 0)) { *why = "rho_wall_field must be > 0 at solid nodes"; return false; }
     }
+    if (p->link_q) {
+        if (!p->mask) { *why = "link_q needs a mask"; return false; }
+        if (!check_link_q(p, why)) return false;
+    }
     return true;
 }
 
@@ -79,6 +122,7 @@ template <class C> inline void fill_params(const lbm_params *p, Params<C> *q) {
     q->eos.b = C(p->b);
     for (int a = 0; a < 3; ++a) q->accel[a] = C(p->accel[a]);
     q->rho_wf = nullptr;   // set by the caller once the wall field is on the device
+    q->link_q = nullptr;   // likewise the link fractions
 }
 
 // device copy of a per-node wall density field in compute precision C (solid entries
@@ -89,6 +133,22 @@ template <class C> inline C *upload_wall_field(const double *host, size_t N) {
     C *d = nullptr;
     if (hipMalloc((void **)&d, N * sizeof(C)) != hipSuccess) return nullptr;
     if (hipMemcpy(d, tmp.data(), N * sizeof(C), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    return d;
+}
+
+// device copy of the wall fractions, [Q][N] host doubles -> [Q][qs] in compute precision
+// (the population stride, so a kernel addresses them like a population array); nullptr
+// on failure
+template <class C> inline C *upload_link_q(const double *host, int Q, size_t N, long long qs) {
+    std::vector<C> tmp((size_t)Q * (size_t)qs, C(0));
+    for (int i = 0; i < Q; ++i)
+        for (size_t n = 0; n < N; ++n) tmp[(size_t)i * (size_t)qs + n] = C(host[(size_t)i * N + n]);
+    C *d = nullptr;
+    if (hipMalloc((void **)&d, tmp.size() * sizeof(C)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, tmp.data(), tmp.size() * sizeof(C), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
         return nullptr;
     }

@@ -1,5 +1,6 @@
 // step_common.hpp -- device code shared by the two-pass and the fused step kernels:
-// pull gather with halfway bounce-back, moments, and the deviation-form collision.
+// pull gather with halfway or interpolated bounce-back, moments, and the deviation-form
+// collision.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -73,10 +74,36 @@ template <class T> __device__ __forceinline__ void st_at(T *__restrict__ base, u
     *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
 }
 
-// pull gather of the Q populations arriving at node n (= r) at this time step
+// Population i arriving at fluid node n whose source n - c_i is solid. Halfway bounce-back
+// returns the opposite post-collision population of n itself. With wall fractions lq
+// ([Q][qs]; the link n -> n - c_i is stored under opp(i)) the linearly interpolated
+// bounce-back of Bouzidi et al. that the paper uses for curved walls (Sec. 4.5, 5.3):
+//   q <  1/2: 2q A_opp(n) + (1 - 2q) A_opp(n + c_i)   (A_opp(n) when n + c_i is solid)
+//   q >= 1/2: A_opp(n) / (2q) + (1 - 1/(2q)) A_i(n)
+// Both weight pairs sum to one and w_i = w_opp(i), so FP32 deviations interpolate as is.
+template <int D, int i, class S, class C>
+__device__ __forceinline__ C wall_pull(const S *__restrict__ A, long long qs, const uint8_t *__restrict__ mask,
+                                       const C *__restrict__ lq, const Nbr<D> &nb, int n) {
+    constexpr int o = opp<D>(i);
+    const C back = C(ld_at(A + o * qs, (unsigned)n));
+    if (!lq) return back;
+    const C q = ld_at(lq + o * qs, (unsigned)n);
+    if (q < C(0.5)) {
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        const unsigned b = (unsigned)nb.at(cx, cy, cz);
+        const C behind = ld_at(mask, b) ? back : C(ld_at(A + o * qs, b));
+        return C(2) * q * back + (C(1) - C(2) * q) * behind;
+    }
+    const C h2q = C(2) * q;
+    return back / h2q + (C(1) - C(1) / h2q) * C(ld_at(A + i * qs, (unsigned)n));
+}
+
+// pull gather of the Q populations arriving at node n (= r) at this time step; lq: wall
+// fractions for interpolated bounce-back, or nullptr (halfway)
 template <int D, class S, class C, bool MASK>
 __device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, const uint8_t *__restrict__ mask,
-                                       const Nbr<D> &nb, int n, C (&h)[Lat<D>::Q]) {
+                                       const Nbr<D> &nb, int n, C (&h)[Lat<D>::Q],
+                                       const C *__restrict__ lq = nullptr) {
     static_for<0, Lat<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
@@ -85,7 +112,7 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, long long qs, co
         } else {
             const unsigned s = (unsigned)nb.at(-cx, -cy, -cz);
             if constexpr (MASK) {
-                h[i] = ld_at(mask, s) ? C(ld_at(A + opp<D>(i) * qs, (unsigned)n)) : C(ld_at(A + i * qs, s));
+                h[i] = ld_at(mask, s) ? wall_pull<D, i, S, C>(A, qs, mask, lq, nb, n) : C(ld_at(A + i * qs, s));
             } else {
                 h[i] = C(ld_at(A + i * qs, s));
             }

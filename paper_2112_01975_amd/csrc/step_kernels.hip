@@ -3,7 +3,9 @@
 //
 // Storage: structure of arrays A[i*qs + n], n = x + nx*(y + ny*z). The array holds
 // post-collision populations at the node that produced them; every pass pulls
-// f_i(r) = A_i(r - c_i), or A_opp(i)(r) when r - c_i is solid (halfway bounce-back).
+// f_i(r) = A_i(r - c_i), or A_opp(i)(r) when r - c_i is solid (halfway bounce-back),
+// or with per-link wall fractions an interpolation of A_opp(i) at r and r + c_i or of
+// A_opp(i) and A_i at r (interpolated bounce-back).
 //
 // Pass 1 (moments): rho = rho_ref + sum h_i, j = sum c_i h_i, g_a = rho u_a^3; FP64
 //   per-workgroup partial sums of mass and momentum for the watchdog.
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g
         } else {
             Nbr<D> nb(g, x, y, z);
             C h[Lat<D>::Q];
-            gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h);
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h, p.link_q);
             C sum, j[3];
             moments_of<D, C>(h, sum, j);
             rho = p.rho_ref + sum;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             });
             continue;
         } else {
-        gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h);
+        gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h, p.link_q);
         C drho, j[3];
         moments_of<D, C>(h, drho, j);
         C u[3] = {C(0), C(0), C(0)};
@@ -228,6 +230,64 @@ __global__ __launch_bounds__(256) void k_prep_rho(C *__restrict__ rho_f, const d
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     rho_f[n] = (MASK && mask[n]) ? wall_density(p, n) : C(rho0[n]);
+}
+
+// Interpolated bounce-back at init. The init kernel folds the equilibrium population i
+// of a fluid node n whose source n - c_i is solid into slot opp(i) at n, which only that
+// wall link reads. The interpolated pull mixes this slot X with a second entry:
+//   q <  1/2: 2q X + (1 - 2q) Y, Y = slot opp(i) at n + c_i (fluid: already f_eq_opp(i)(n);
+//             solid: the pull uses X alone)
+//   q >= 1/2: a X + (1 - a) Z,  a = 1/(2q), Z = slot i at n (n + c_i fluid: already the
+//             equilibrium pulled there; solid: the slot X' of the opposite wall link)
+// so X is re-solved for the pull to return the folded value P; the opposite-pair case is a
+// 2x2 system with determinant a + a' - 1 (bounded away from 0 by host validation). Only
+// the node's own wall slots change, and every entry read is either one of them, read
+// before any write, or a regular entry, so nodes are independent.
+template <int D, class S, class C>
+__global__ __launch_bounds__(256) void k_wall_init(S *__restrict__ A, Geom g, const uint8_t *__restrict__ mask,
+                                                   const C *__restrict__ lq) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= g.N || mask[n]) return;
+    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+    Nbr<D> nb(g, x, y, z);
+    constexpr int Q = Lat<D>::Q;
+    C P[Q], X[Q];
+    bool wall[Q];
+    static_for<1, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        wall[i] = mask[nb.at(-cx, -cy, -cz)] != 0;
+        P[i] = wall[i] ? C(A[(long long)opp<D>(i) * g.qs + n]) : C(0);
+    });
+    static_for<1, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value, o = opp<D>(i);
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        X[i] = P[i];
+        if (!wall[i]) return;
+        const C q = lq[(long long)o * g.qs + n];
+        const int b = nb.at(cx, cy, cz);
+        const bool bsolid = mask[b] != 0;   // n + c_i solid <=> (n, opp(i)) is a wall link too
+        if (q < C(0.5)) {
+            if (!bsolid) X[i] = (P[i] - (C(1) - C(2) * q) * C(A[(long long)o * g.qs + b])) / (C(2) * q);
+            return;
+        }
+        const C a = C(1) / (C(2) * q);
+        if (!bsolid) {
+            X[i] = (P[i] - (C(1) - a) * C(A[(long long)i * g.qs + n])) / a;
+            return;
+        }
+        const C q2 = lq[(long long)i * g.qs + n];
+        if (q2 < C(0.5)) {                   // the opposite link keeps its folded value
+            X[i] = (P[i] - (C(1) - a) * P[o]) / a;
+            return;
+        }
+        const C a2 = C(1) / (C(2) * q2);
+        X[i] = (a2 * P[i] - (C(1) - a) * P[o]) / (a + a2 - C(1));
+    });
+    static_for<1, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (wall[i]) A[(long long)opp<D>(i) * g.qs + n] = S(X[i]);
+    });
 }
 
 template <class S> __global__ __launch_bounds__(256) void k_fill_zero(S *__restrict__ A, long long count) {
@@ -276,6 +336,10 @@ template <int D, class S, class C, bool MASK> struct Launch {
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_INIT>), collide_grid(g), dim3(256), 0, s,
                            (const S *)nullptr, (S *)A, g, mask, p, (const C *)rho, (const C *)nullptr,
                            (double *)nullptr, (double *)U0);
+        if constexpr (MASK)
+            if (p.link_q)
+                hipLaunchKernelGGL((k_wall_init<D, S, C>), dim3((g.N + 255) / 256), dim3(256), 0, s, (S *)A, g, mask,
+                                   p.link_q);
     }
     static void moments(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm, void *rho,
                         void *gfl, double *partials) {

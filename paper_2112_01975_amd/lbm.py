@@ -44,7 +44,7 @@ class lbm_params(C.Structure):
         ("tau_liquid", C.c_double), ("tau_vapour", C.c_double),
         ("rho_liquid", C.c_double), ("rho_vapour", C.c_double), ("rho_wall", C.c_double),
         ("mask", C.c_void_p), ("precision", C.c_int), ("rho_ref", C.c_double), ("check_every", C.c_int),
-        ("accel", C.c_double * 3), ("rho_wall_field", C.c_void_p),
+        ("accel", C.c_double * 3), ("rho_wall_field", C.c_void_p), ("link_q", C.c_void_p),
     ]
 
 
@@ -131,6 +131,7 @@ class Params:
     check_every: int = 0
     accel: tuple = (0.0, 0.0, 0.0)
     rho_wall_field: np.ndarray | None = None
+    link_q: np.ndarray | None = None       # [Q][N] wall fractions in lbm_velocities order
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -144,12 +145,13 @@ class Params:
     def to_c(self) -> lbm_params:
         m = None if self.mask is None else np.ascontiguousarray(self.mask, dtype=np.uint8)
         wf = None if self.rho_wall_field is None else np.ascontiguousarray(self.rho_wall_field, dtype=np.float64)
-        self._keep = [m, wf]
+        lq = None if self.link_q is None else np.ascontiguousarray(self.link_q, dtype=np.float64)
+        self._keep = [m, wf, lq]
         return lbm_params(self.lattice, self.nx, self.ny, self.nz, self.eos, self.a, self.b, self.R,
                           self.acentric, self.T_reduced, self.kappa, self.tau_liquid, self.tau_vapour,
                           self.rho_liquid, self.rho_vapour, self.rho_wall, _ptr(m), self.precision,
                           self.rho_ref, self.check_every, (C.c_double * 3)(*[float(g) for g in self.accel]),
-                          _ptr(wf))
+                          _ptr(wf), _ptr(lq))
 
 
 # ----------------------------------------------------------------- C-named wrappers

@@ -34,6 +34,7 @@ class Case:
     mask: np.ndarray | None = None
     accel: tuple = (0.0, 0.0, 0.0)
     rho_wall_field: np.ndarray | None = None
+    link_q: np.ndarray | None = None    # [3,3(,3),N] wall fraction of the link n -> n + c, indexed by c + 1
 
     @property
     def N(self):
@@ -49,7 +50,7 @@ class Case:
         rv, rl = self.coexistence() if self.eos != T.IDEAL else (1.0, 1.0)
         return O.Config(self.lattice, self.nx, self.ny, self.nz, self.eos, self.a, self.b, 1.0, self.acentric,
                         self.T_reduced, self.kappa, self.tau, self.tau_vapour, rl, rv, self.rho_wall,
-                        accel=self.accel, rho_wall_field=self.rho_wall_field)
+                        accel=self.accel, rho_wall_field=self.rho_wall_field, link_q=self.link_q)
 
     def params(self, precision=0, rho_ref=0.0, check_every=0):
         import paper_2112_01975_amd as P
@@ -57,7 +58,16 @@ class Case:
         return P.Params(P.LBM_D3Q27 if self.lattice == 3 else P.LBM_D2Q9, self.nx, self.ny, self.nz,
                         EOS_OF[self.eos], self.a, self.b, 1.0, self.acentric, self.T_reduced, self.kappa,
                         self.tau, self.tau_vapour, rl, rv, self.rho_wall, self.mask, precision, rho_ref,
-                        check_every, self.accel, self.rho_wall_field)
+                        check_every, self.accel, self.rho_wall_field, self.library_link_q())
+
+    def library_link_q(self):
+        """link_q as the library takes it: [Q][N] in lbm_velocities order."""
+        if self.link_q is None:
+            return None
+        import paper_2112_01975_amd as P
+        cl = P.lbm_velocities(P.LBM_D3Q27 if self.lattice == 3 else P.LBM_D2Q9)
+        cube = np.asarray(self.link_q, dtype=np.float64).reshape((3,) * self.lattice + (self.N,))
+        return np.stack([cube[tuple(int(cl[i, a]) + 1 for a in range(self.lattice))] for i in range(len(cl))])
 
 
 def run_oracle(case: Case, rho0, u0, steps):

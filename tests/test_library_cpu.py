@@ -51,6 +51,13 @@ def test_no_loop_above_critical_temperature_is_a_domain_error():
     assert ei.value.code == P.LBM_E_DOMAIN
 
 
+def _wall_rows(rows, q):
+    """64x64 D2Q9 grid with solid rows at the given y, and every link fraction set to q."""
+    m = np.zeros((64, 64), np.uint8)
+    m[list(rows)] = 1
+    return dict(mask=m.ravel(), rho_wall=1.0, link_q=np.full((9, 64 * 64), q))
+
+
 @pytest.mark.parametrize("bad,msg", [
     (dict(lattice=7), "lattice"),
     (dict(nz=2), "nz == 1"),
@@ -64,6 +71,10 @@ def test_no_loop_above_critical_temperature_is_a_domain_error():
     (dict(tau_vapour=0.4), "tau_vapour"),
     (dict(tau_vapour=0.9, rho_liquid=1.0, rho_vapour=2.0), "variable viscosity"),
     (dict(mask=np.zeros(64 * 64, np.uint8), rho_wall=0.0), "rho_wall"),
+    (dict(link_q=np.full((9, 64 * 64), 0.5)), "link_q needs a mask"),
+    (_wall_rows((0,), 0.0), "(0, 1]"),
+    (_wall_rows((0,), 1.5), "(0, 1]"),
+    (_wall_rows((10, 12), 1.0), "1.01"),          # row 11 cut on both sides at q = 1
 ])
 def test_create_rejects_bad_parameters_without_gpu(bad, msg):
     import paper_2112_01975_amd as P
@@ -75,3 +86,11 @@ def test_create_rejects_bad_parameters_without_gpu(bad, msg):
     assert ei.value.code == P.LBM_E_INVAL
     assert msg in str(ei.value)
     assert msg in P.lbm_last_error(None)
+
+
+def test_batch_rejects_interpolated_walls_without_gpu():
+    import paper_2112_01975_amd as P
+    p = P.Params(P.LBM_D2Q9, 64, 64, 1, **_wall_rows((0,), 0.5))
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_batch_create([p])
+    assert ei.value.code == P.LBM_E_INVAL and "not supported by the batch" in str(ei.value)
