@@ -200,7 +200,47 @@ def other_workloads(P, torch):
         mlups, ok = timed_mlups(P, torch, p, rho0, U0, 50, 5)
         d3[name] = {"MLUPS": mlups, "MFLUPS": mlups * fluid / p.N, "finite": ok}
     out["d3q27_512x256x256_impact"] = {"steps": 50, "fluid_nodes": fluid, "nodes": nx * ny * nz, **d3}
+    out["d3q27_256_tapered_posts"] = tapered_posts_workload(P, torch, a3)
     return out
+
+
+def tapered_posts_workload(P, torch, a3, d0=64):
+    """Drop impact on tapered posts with curved walls: a 4 D0 box (256^3 at D0 = 64), solid
+    floor 2 nodes thick, 8 x 8 cone-frustum posts every D0/2 (base radius 0.15 D0, tip
+    0.05 D0, height D0/2), a drop of diameter D0 whose lowest point is 10 nodes above the
+    post tops, moving at -0.05 along z; Peng-Robinson T/Tc = 0.6 as the impact workload,
+    wall density = vapour density. Interpolated bounce-back with the exact cut fraction of
+    every wall link (two-pass step), FP32 and FP64; the same geometry with halfway
+    bounce-back (fused step) for comparison."""
+    import lbm_inputs as L
+    n = 4 * d0
+    t0 = time.perf_counter()
+    mask, lq_cube = L.tapered_posts(n, n, n, 2, 0.15 * d0, 0.05 * d0, 0.5 * d0, d0 // 2)
+    t_geom = time.perf_counter() - t0
+    cl = P.lbm_velocities(P.LBM_D3Q27)
+    link_q = np.stack([lq_cube[int(c[0]) + 1, int(c[1]) + 1, int(c[2]) + 1] for c in cl])
+    del lq_cube
+    fluid = int((mask == 0).sum())
+    wall_links = int((link_q > 0).sum())
+    top = 1.5 + 0.5 * d0
+    res = {"nodes": n ** 3, "fluid_nodes": fluid, "wall_links": wall_links, "steps": 50,
+           "geometry_s": t_geom}
+    rho0 = U0 = None
+    for prec, name, lq in ((P.LBM_FP32_DEV, "fp32", link_q), (P.LBM_FP64, "fp64", link_q),
+                           (P.LBM_FP32_DEV, "fp32_halfway", None)):
+        p = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_PR, a3, B21, 1.0, 0.344, 0.6, 0.02, 0.55,
+                     tau_vapour=0.5 + 15 * 0.05, mask=mask, precision=prec, check_every=-1, link_q=lq)
+        rv, rl, _, _ = P.lbm_coexistence(p)
+        p.rho_liquid, p.rho_vapour, p.rho_wall = rl, rv, rv
+        p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
+        if rho0 is None:
+            rho0 = L.drop(n, n, n, 0.5 * d0, rl, rv, 5.0, centre=(n / 2, n / 2, top + 10.0 + 0.5 * d0),
+                          noise=1e-5, seed=1007)
+            rho0 = np.where(mask.astype(bool), rv, rho0)
+            U0 = L.impact_drop_velocity(rho0, rl, rv, 3, -0.05, 2)
+        mlups, ok = timed_mlups(P, torch, p, rho0, U0, 50, 5)
+        res[name] = {"MLUPS": mlups, "MFLUPS": mlups * fluid / p.N, "finite": ok}
+    return res
 
 
 def cpu_baseline(budget_s=12.0):
@@ -236,7 +276,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
-    ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2 and drop-impact legs")
+    ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2, drop-impact and posts legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -292,7 +332,7 @@ def main():
         log(f"[bench] batch {batch['batched_s']:.3f} s vs one-by-one {batch['one_by_one_s']:.3f} s")
     other = None
     if not args.no_other:
-        log("[bench] other workloads (D2Q9 512^2, D3Q27 512x256x256 impact)")
+        log("[bench] other workloads (D2Q9 512^2, D3Q27 512x256x256 impact, 256^3 tapered posts)")
         other = other_workloads(P, torch)
         log(f"[bench] other {json.dumps(other)}")
     cpu = None

@@ -158,6 +158,80 @@ def sphere_obstacle(nx: int, ny: int, nz: int, centre, radius: float):
     return solid.astype(np.uint8), lq
 
 
+def _link_fractions(along, solid: np.ndarray, dims, iters: int = 30) -> np.ndarray:
+    """Wall fractions of every link from a fluid node into a solid node, by bisection of
+    an implicit surface along the link, to 2^-30. along(px, py, pz, c) returns phi(t) for
+    the links from nodes (px, py, pz) in direction c: phi(t) <= 0 inside the solid,
+    phi(0) > 0 >= phi(1). solid: bool [N]. Returns the (3,)*D + (N,) array of
+    sphere_obstacle (zero away from walls)."""
+    D = len(dims)
+    nx, ny, nz = (tuple(dims) + (1,))[:3]
+    N = nx * ny * nz
+    lq = np.zeros((3,) * D + (N,))
+    s3 = solid.reshape(nz, ny, nx)
+    fluid = ~s3
+    for c in itertools.product((-1, 0, 1), repeat=D):
+        if not any(c):
+            continue
+        cz = c[2] if D == 3 else 0
+        ahead = np.roll(s3, (-cz, -c[1], -c[0]), axis=(0, 1, 2))       # solid at r + c
+        n = np.flatnonzero(ahead & fluid)
+        if n.size == 0:
+            continue
+        phi = along((n % nx).astype(np.float64), ((n // nx) % ny).astype(np.float64),
+                    (n // (nx * ny)).astype(np.float64), (c[0], c[1], cz))
+        lo = np.zeros(n.size)
+        hi = np.ones(n.size)
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            inside = phi(mid) <= 0
+            hi = np.where(inside, mid, hi)
+            lo = np.where(inside, lo, mid)
+        lq[tuple(ci + 1 for ci in c)][n] = np.clip(hi, 1e-6, 1.0)
+    return lq
+
+
+def tapered_posts(nx: int, ny: int, nz: int, floor: int, r_base: float, r_tip: float, height: float,
+                  spacing: int):
+    """Flat substrate with tapered posts in a square arrangement (the curved-wall geometry of
+    drops bouncing off tapered posts), z vertical.
+
+    The solid floor is the nodes z < floor, its surface the plane z = floor - 1/2; because
+    z is periodic the floor is also a ceiling, with the surface z = nz - 1/2. Each
+    spacing x spacing cell holds one post on its centre axis: a cone frustum standing on
+    the floor surface, radius r_base there, r_tip at the top, height `height`
+    (r_base < spacing/2 - 1, so no link reaches a post across a cell edge). nx and ny must
+    be multiples of spacing. Returns (mask uint8 [N], link_q (3,3,3,N)) with exact cut
+    fractions as in sphere_obstacle.
+    """
+    if nx % spacing or ny % spacing:
+        raise ValueError("nx and ny must be multiples of the post spacing")
+    if not (0 < r_tip and 0 < r_base < 0.5 * spacing - 1):
+        raise ValueError("post radii must be positive and below spacing/2 - 1")
+    zf = floor - 0.5
+    ztop = zf + height
+    half = 0.5 * spacing
+    slope = (r_tip - r_base) / height
+
+    def phi_at(rx, ry, zw):
+        # zw: height with the floor slab at [-1/2, zf] (a link across the top of the box
+        # starts at zw = -1); rx, ry from the post axis; posts stand on the slab
+        slab = np.maximum(zw - zf, -0.5 - zw)
+        post = np.maximum(np.sqrt(rx * rx + ry * ry) - (r_base + slope * (zw - zf)),
+                          np.maximum(zw - ztop, -0.5 - zw))
+        return np.minimum(slab, post)
+
+    def along(px, py, pz, c):
+        rx = np.mod(px, spacing) - half         # the link's own cell: posts never cross an edge
+        ry = np.mod(py, spacing) - half
+        zw = np.where(pz + 0.5 * c[2] >= nz - 0.5, pz - nz, pz)   # the link crosses z = nz - 1/2
+        return lambda t: phi_at(rx + t * c[0], ry + t * c[1], zw + t * c[2])
+
+    x, y, z = _grid(nx, ny, nz)
+    solid = phi_at(np.mod(x, spacing) - half, np.mod(y, spacing) - half, z) <= 0
+    return solid.astype(np.uint8), _link_fractions(along, solid, (nx, ny, nz))
+
+
 def random_state(N: int, D: int, rho_lo: float, rho_hi: float, umax: float, seed: int):
     """Random density in [rho_lo, rho_hi) and velocity components in [-umax, umax)."""
     u01 = (splitmix64(seed, N) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)

@@ -17,12 +17,15 @@ struct FusedGrid {
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz);
 
-// Solid geometry for the fused step (both nullptr without solid nodes):
+// Solid geometry for the fused step (nullptr without solid nodes):
 //   links[n]  per-node solid-neighbour bits from fused_links;
-//   pflags[z] bit 0: plane z has a solid node, bit 1: planes z-1..z+1 have one.
+//   pflags[z] bit 0: plane z has a solid node, bit 1: planes z-1..z+1 have one;
+//   qlo[n]    with interpolated walls only: bit i when the wall link crossed by
+//             population i has q < 1/2 (fused_qlo).
 struct FusedMask {
     const uint32_t *links;
     const uint32_t *pflags;
+    const uint32_t *qlo;
 };
 
 using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, const FusedMask &,
@@ -31,8 +34,12 @@ using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, 
 // bit i of links[n]: the source node n - c_i of population i is solid; bit 27: n is solid
 void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g);
 
+// the q < 1/2 bits from the links and the device wall fractions ([Q][qs], compute precision)
+void fused_qlo(hipStream_t s, const uint32_t *links, const void *lq, bool fp64, uint32_t *qlo, const Geom &g);
+
 // nullptr when no fused variant exists for this combination
-// split: the lattice exceeds one buffer resource (4 GiB) and is addressed as two
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split);
+// split: the lattice exceeds one buffer resource (4 GiB) and is addressed as two;
+// interp: walls with per-link fractions (Params::link_q), interpolated bounce-back
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split, bool interp);
 
 }  // namespace lbm

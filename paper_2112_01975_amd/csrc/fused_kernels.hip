@@ -143,6 +143,64 @@ __device__ __forceinline__ C pull(const LT &A, uint32_t lm, const Stencil &st, c
     }
 }
 
+// Interpolated bounce-back over the pulled populations h of the node at stencil st in
+// plane zs[1] (links lm): a pull across a wall link returned A_opp(i) of the node itself
+// (halfway); with the link's wall fraction q (lq, [Q][qs], stored under opp(i)) it
+// becomes the linear interpolation of Bouzidi et al. used for curved walls (Sec. 4.5,
+// 5.3): q < 1/2 mixes in A_opp(i) of the node n + c_i behind (unless that node is
+// solid), q >= 1/2 mixes in A_i of the node itself. Lanes without wall links skip it.
+// k-th link (k = 0.., rest excluded) with z component cz, in library order
+constexpr int zlink(int cz, int k) {
+    for (int i = 1; i < 27; ++i)
+        if (Lat<3>::c(i, 2) == cz && k-- == 0) return i;
+    return -1;
+}
+
+// Links go in three groups by c_z (a floor or ceiling node only crosses one of them)
+// without branches inside a group: the fractions and the partner values of a group (the
+// partner's address chosen per lane by the precomputed bit qlo_i = (q < 1/2)) are loaded
+// together and then selected, so a wall node waits for one load latency per group it
+// needs instead of two per link; a group no lane of the wave needs is skipped.
+template <class S, class C, int CZ, class LT>
+__device__ __forceinline__ void interp_group(const LT &A, const C *__restrict__ lq, long long qs, unsigned n,
+                                             uint32_t lm, uint32_t qlo, const Stencil &st, const unsigned (&zs)[3],
+                                             C (&h)[27]) {
+    constexpr int K = CZ == 0 ? 8 : 9;
+    constexpr uint32_t gmask = [] {
+        uint32_t m = 0;
+        for (int k = 0; k < K; ++k) m |= 1u << zlink(CZ, k);
+        return m;
+    }();
+    if (!(lm & gmask)) return;
+    C qv[K], xv[K];
+    static_for<0, K>([&](auto I) {
+        constexpr int k = decltype(I)::value, i = zlink(CZ, k), o = opp<3>(i);
+        constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+        qv[k] = lq[(long long)o * qs + n];
+        // population o of n + c_i, or (q >= 1/2) population opp(o) = i of n itself
+        xv[k] = C(A.template load_or_bounce<o>(!((qlo >> i) & 1u), st.v[1 + cx][1 + cy], zs[1 + cz], st.v[1][1],
+                                               zs[1]));
+    });
+    static_for<0, K>([&](auto I) {
+        constexpr int k = decltype(I)::value, i = zlink(CZ, k), o = opp<3>(i);
+        const C q = qv[k], back = h[i], x = xv[k];
+        const C h2q = C(2) * q;
+        const C lo = ((lm >> o) & 1u) ? back : h2q * back + (C(1) - h2q) * x;
+        const C hi = back / h2q + (C(1) - C(1) / h2q) * x;
+        if ((lm >> i) & 1u) h[i] = ((qlo >> i) & 1u) ? lo : hi;
+    });
+}
+
+template <class S, class C, class LT>
+__device__ __forceinline__ void interp_walls(const LT &A, const C *__restrict__ lq, long long qs, uint32_t lm,
+                                             uint32_t qlo, const Stencil &st, const unsigned (&zs)[3], C (&h)[27]) {
+    if (!(lm & ((1u << 27) - 2u))) return;
+    const unsigned n = (st.v[1][1] + zs[1]) / (unsigned)sizeof(S);
+    interp_group<S, C, 1>(A, lq, qs, n, lm, qlo, st, zs, h);
+    interp_group<S, C, 0>(A, lq, qs, n, lm, qlo, st, zs, h);
+    interp_group<S, C, -1>(A, lq, qs, n, lm, qlo, st, zs, h);
+}
+
 template <class S, class C, bool MASK, class LT>
 __device__ __forceinline__ void pull_all(const LT &A, uint32_t lm, const Stencil &st, const unsigned (&zs)[3],
                                          C (&h)[27]) {
@@ -152,7 +210,7 @@ __device__ __forceinline__ void pull_all(const LT &A, uint32_t lm, const Stencil
     });
 }
 
-template <class S, class C, bool MASK, int FTX, int TY, bool REPULL, bool SPLIT2>
+template <class S, class C, bool MASK, int FTX, int TY, bool REPULL, bool SPLIT2, bool INTERP>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                       FusedMask fm, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
@@ -234,6 +292,16 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     auto links_at = [&](const Stencil &st, const unsigned (&zs)[3]) __attribute__((always_inline)) {
         return fm.links[(st.v[1][1] + zs[1]) / SB];
     };
+    // interpolated walls (INTERP) on a node's pulled populations; only bodies whose pulls
+    // may bounce back (MM) call it
+    auto fix = [&](const LT &src, uint32_t lm, uint32_t qlo, const Stencil &st, const unsigned (&zs)[3], C (&h)[27])
+        __attribute__((always_inline)) {
+        if constexpr (INTERP) interp_walls<S, C>(src, p.link_q, g.qs, lm, qlo, st, zs, h);
+    };
+    // the q < 1/2 bits of the node of stencil st in plane zs[1] (INTERP only)
+    auto qlo_at = [&](const Stencil &st, const unsigned (&zs)[3]) __attribute__((always_inline)) {
+        return INTERP ? fm.qlo[(st.v[1][1] + zs[1]) / SB] : 0u;
+    };
     // per-plane solid flags (uniform): bit 0 plane pz has a solid node, bit 1 planes pz-1..pz+1 do,
     // i.e. some pull of plane pz may bounce back
     auto plane_flags = [&](int pz) __attribute__((always_inline)) {
@@ -281,13 +349,19 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const int slot = ((j + 2) % RING) * HP, buf = (j + 2) & 1;
         const uint32_t lm = MM ? links_at(si, zs) : 0u;
         const bool solid = (lm >> LINK_SELF) & 1u;
-        if (!solid) pull_all<S, C, MM>(Ab, lm, si, zs, h);
+        if (!solid) {
+            pull_all<S, C, MM>(Ab, lm, si, zs, h);
+            if constexpr (MM) fix(Ab, lm, qlo_at(si, zs), si, zs, h);
+        }
         const C gzn = stage(e_int, solid, (si.v[1][1] + zs[1]) / SB, h, m, slot, buf);
         if (has_halo) {
             C hh[27], mh[4];
             const uint32_t lh = MM ? links_at(sh, zs) : 0u;
             const bool hs = (lh >> LINK_SELF) & 1u;
-            if (!hs) pull_all<S, C, MM>(Ab, lh, sh, zs, hh);
+            if (!hs) {
+                pull_all<S, C, MM>(Ab, lh, sh, zs, hh);
+                if constexpr (MM) fix(Ab, lh, qlo_at(sh, zs), sh, zs, hh);
+            }
             stage(e_halo, hs, (sh.v[1][1] + zs[1]) / SB, hh, mh, slot, buf);
         }
         __syncthreads();
@@ -310,8 +384,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const bool halo = has_halo && need3;
         C hh[27];
         const uint32_t lh = MM && halo ? links_at(sh, zs3) : 0u;
+        const uint32_t bh = MM && halo ? qlo_at(sh, zs3) : 0u;
         if (halo && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
         const uint32_t l3 = MM ? links_at(si, zs3) : 0u;
+        const uint32_t b3 = MM && need3 ? qlo_at(si, zs3) : 0u;
 
         const unsigned zoff = (unsigned)(nxy * (z < g.nz ? z : 0)) * SB;
         const bool act = own && z < g.nz &&
@@ -321,8 +397,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             unsigned zsz[3];
             planes(z, zsz);
             if (act) {
-                if (MASK && (plane_flags(z) & 2u)) pull_all<S, C, MASK>(Ab, links_at(si, zsz), si, zsz, qa);
-                else pull_all<S, C, false>(Ab, 0u, si, zsz, qa);
+                if (MASK && (plane_flags(z) & 2u)) {
+                    const uint32_t lz = links_at(si, zsz);
+                    pull_all<S, C, MASK>(Ab, lz, si, zsz, qa);
+                    fix(Ab, lz, qlo_at(si, zsz), si, zsz, qa);
+                } else {
+                    pull_all<S, C, false>(Ab, 0u, si, zsz, qa);
+                }
             }
         }
         C Sf[3] = {C(0), C(0), C(0)};
@@ -353,6 +434,8 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         }
         if (halo) {
             C mh[4];
+            if constexpr (MM)
+                if (!((lh >> LINK_SELF) & 1u)) fix(Ab, lh, bh, sh, zs3, hh);
             stage(e_halo, (lh >> LINK_SELF) & 1u, (sh.v[1][1] + zs3[1]) / SB, hh, mh, slot, buf);
         }
 
@@ -415,6 +498,8 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             pull_all<S, C, MM>(src, l3, si, zs3, qa);
         }
         C gzn = C(0);
+        if constexpr (MM)
+            if (need3 && !((l3 >> LINK_SELF) & 1u)) fix(Ab, l3, b3, si, zs3, qa);
         if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, (si.v[1][1] + zs3[1]) / SB, qa, ma, slot, buf);
         __syncthreads();
         shift_windows(gzn, buf);
@@ -451,11 +536,11 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     }
 }
 
-template <class S, class C, bool MASK, int TX, int TY, bool REPULL, bool SPLIT2>
+template <class S, class C, bool MASK, int TX, int TY, bool REPULL, bool SPLIT2, bool INTERP = false>
 void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const FusedMask &fm, const void *prm,
                   const FusedGrid &fg) {
-    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL, SPLIT2>), dim3(fg.blocks), dim3(TX * TY), 0, s, (const S *)A, (S *)B, g,
-                       fm, *(const Params<C> *)prm, fg);
+    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL, SPLIT2, INTERP>), dim3(fg.blocks), dim3(TX * TY), 0, s,
+                       (const S *)A, (S *)B, g, fm, *(const Params<C> *)prm, fg);
 }
 
 __global__ void k_links(const uint8_t *__restrict__ mask, uint32_t *__restrict__ links, Geom g) {
@@ -472,10 +557,33 @@ __global__ void k_links(const uint8_t *__restrict__ mask, uint32_t *__restrict__
     links[n] = b;
 }
 
+// bit i set when population i of fluid node n crosses a wall link whose fraction (stored
+// under opp(i)) is below 1/2, compared in the compute precision C of the step
+template <class C>
+__global__ void k_qlo(const uint32_t *__restrict__ links, const C *__restrict__ lq, uint32_t *__restrict__ qlo, Geom g) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const uint32_t lm = links[n];
+    uint32_t b = 0u;
+    if (!((lm >> LINK_SELF) & 1u))
+        static_for<1, 27>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if (((lm >> i) & 1u) && lq[(long long)opp<3>(i) * g.qs + n] < C(0.5)) b |= 1u << i;
+        });
+    qlo[n] = b;
+}
+
 }  // namespace
 
 void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g) {
     hipLaunchKernelGGL(k_links, dim3((g.N + 255) / 256), dim3(256), 0, s, mask, links, g);
+}
+
+void fused_qlo(hipStream_t s, const uint32_t *links, const void *lq, bool fp64, uint32_t *qlo, const Geom &g) {
+    if (fp64)
+        hipLaunchKernelGGL(k_qlo<double>, dim3((g.N + 255) / 256), dim3(256), 0, s, links, (const double *)lq, qlo, g);
+    else
+        hipLaunchKernelGGL(k_qlo<float>, dim3((g.N + 255) / 256), dim3(256), 0, s, links, (const float *)lq, qlo, g);
 }
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
@@ -499,7 +607,14 @@ template <int TX, int TY> FusedLaunch pick(bool masked) {
 }
 }  // namespace
 
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split) {
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split, bool interp) {
+    if (interp) {   // interpolated walls: masked 64 x 8 variants only
+        if (!masked || tx != 64 || ty != 8) return nullptr;
+        if (fp64)
+            return split ? launch_fused<double, double, true, 64, 8, true, true, true>
+                         : launch_fused<double, double, true, 64, 8, true, false, true>;
+        return split ? nullptr : launch_fused<float, float, true, 64, 8, false, false, true>;
+    }
     if (fp64) {
         if (tx != 64 || ty != 8) return nullptr;
         if (split)

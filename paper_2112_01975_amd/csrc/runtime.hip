@@ -31,6 +31,7 @@ struct lbm_ctx {
     uint8_t *mask = nullptr;
     uint32_t *links = nullptr;       // solid-neighbour bits for the fused step (masked only)
     uint32_t *pflags = nullptr;      // per-plane solid flags for the fused step (masked only)
+    uint32_t *qlo = nullptr;         // q < 1/2 bits of the wall links for the fused step (link_q only)
     void *wall = nullptr;            // per-node wall densities in compute precision (optional)
     void *lq = nullptr;              // per-link wall fractions in compute precision (optional)
     double *partials = nullptr, *totals = nullptr;
@@ -67,7 +68,8 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
-    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->wall, c->lq, c->partials, c->totals, c->io};
+    void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->qlo, c->wall, c->lq, c->partials,
+                    c->totals, c->io};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -102,7 +104,7 @@ int watchdog(lbm_ctx *c) {
 
 int one_step(lbm_ctx *c) {
     if (c->fused) {
-        c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags}, params_ptr(c), c->fg);
+        c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), c->fg);
     } else {
         c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
@@ -144,9 +146,8 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     // single-pass z-march for D3Q27 (LBM2P_TWO_PASS=1 forces the two-pass step;
     // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length). By default
     // the z-chunks are as long as possible while every CU still gets a work item: each
-    // chunk re-reads a four-plane z halo and runs a five-plane prologue. Interpolated
-    // bounce-back (link_q) runs in the two-pass step only.
-    if (c->D == 3 && !p->link_q && !env_int("LBM2P_TWO_PASS", 0)) {
+    // chunk re-reads a four-plane z halo and runs a five-plane prologue.
+    if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
         const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
         int cus = 256;
         {
@@ -165,7 +166,7 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         const unsigned long long whole = 27ull * (unsigned long long)c->g.qs * c->sbytes;
         const unsigned long long part = 14ull * (unsigned long long)c->g.qs * c->sbytes;
         if (part < 0xFFFFFFFFull) {
-            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, whole >= 0xFFFFFFFFull);
+            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, whole >= 0xFFFFFFFFull, p->link_q != nullptr);
             if (c->fused) c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
         }
     }
@@ -221,6 +222,13 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
                 return fail(nullptr, LBM_E_NOMEM, "device allocation of the link mask failed");
             }
             fused_links(c->stream, c->mask, c->links, c->g);
+            if (c->lq) {   // which partner each interpolated wall link reads
+                if (hipMalloc((void **)&c->qlo, N * sizeof(uint32_t)) != hipSuccess) {
+                    free_ctx(c);
+                    return fail(nullptr, LBM_E_NOMEM, "device allocation of the wall-link bits failed");
+                }
+                fused_qlo(c->stream, c->links, c->lq, c->fp64, c->qlo, c->g);
+            }
             const int nz = c->g.nz, nxy = c->g.nx * c->g.ny;
             std::vector<uint32_t> has(nz, 0u), pf(nz, 0u);
             for (int z = 0; z < nz; ++z)
@@ -302,7 +310,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
             c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
         if (c->fused)
-            c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags}, params_ptr(c), c->fg);
+            c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), c->fg);
         else
             c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
         HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));

@@ -145,3 +145,53 @@ def test_flow_past_a_sphere_d3q27_fp64_and_fp32():
     fl_ = ~mask.astype(bool)
     assert max_rel(r32[fl_], r_o[fl_]) < 1e-5
     assert np.abs(U32 - U_o).max() < 1e-3 * np.abs(U_o).max()
+
+
+def _posts_case(nx, ny, nz, precision_tau_v=0.0):
+    mask, lq = L.tapered_posts(nx, ny, nz, 2, 4.5, 2.0, 12.0, 16)
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6, rho_wall=0.0102306,
+                mask=mask, link_q=lq, tau_vapour=precision_tau_v)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(nx, ny, nz, 10.0, rl, rv, 5.0, centre=(nx / 2, ny / 2, 26.0), noise=1e-5, seed=1009)
+    rho0 = np.where(mask.astype(bool), rv, rho0)
+    return case, rho0, L.impact_drop_velocity(rho0, rl, rv, 3, -0.05, 2), rv
+
+
+@pytest.mark.parametrize("geometry", ["random", "posts"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_interpolated_walls_match_two_pass(geometry, precision, monkeypatch):
+    # the z-march with interpolated walls against the two-pass step on the same inputs:
+    # random solids with random fractions on ragged tiles, and tapered posts with exact cut
+    # fractions under an impacting drop; several z-chunks with a ragged last one. FP64:
+    # the same arithmetic up to the order of a few sums; FP32 as the halfway comparison
+    if geometry == "random":
+        case, rho0, u0, (rv, _) = _random_walls(3, 48, 20, 36, 91)
+    else:
+        case, rho0, u0, rv = _posts_case(64, 32, 40, 1.25 if precision == 0 else 0.0)
+    rr = rv if precision else 0.0
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "16")
+    fused = run_gpu(case, rho0, u0, 30, precision=precision, rho_ref=rr)
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    two = run_gpu(case, rho0, u0, 30, precision=precision, rho_ref=rr)
+    assert np.all(np.isfinite(fused[0]))
+    if precision == 0:
+        assert max_rel(fused[0], two[0]) < 1e-12
+        assert np.abs(fused[1] - two[1]).max() < 1e-13
+    else:
+        assert max_rel(fused[0], two[0]) < 1e-5
+        assert np.abs(fused[1] - two[1]).max() < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tapered_posts_impact_fused_matches_oracle(precision):
+    # the posts geometry through the default (fused) path against the oracle: FP64 to the
+    # parity bar, FP32 density within 1e-5 and velocity within 1e-5 absolute after 40 steps
+    case, rho0, u0, rv = _posts_case(32, 32, 40)
+    r_o, U_o, _ = run_oracle(case, rho0, u0, 40)
+    if precision == 0:
+        r_g, U_g, _ = run_gpu(case, rho0, u0, 40)
+        assert max_rel(r_g, r_o) <= FP64_RHO_TOL and np.abs(U_g - U_o).max() <= FP64_U_TOL
+    else:
+        r_g, U_g, _ = run_gpu(case, rho0, u0, 40, precision=1, rho_ref=rv)
+        fl = ~case.mask.astype(bool)
+        assert max_rel(r_g[fl], r_o[fl]) < 1e-5 and np.abs(U_g - U_o).max() < 1e-5

@@ -627,3 +627,42 @@ def test_initial_state_reproduces_the_flow_velocity():
     cfg.variant = O.VARIANT_INIT_BARE_U
     _, U2, _ = O.Oracle(cfg).init(rho, U).moments()
     assert np.abs(U2 - U).max() > 1e-3
+
+
+# ------------------------------------------------------------------ wall geometry inputs
+def test_sphere_link_fractions_match_bisection_and_geometry():
+    # closed-form cut fractions of the sphere generator against an independent bisection,
+    # and an axis link whose cut point is known by hand
+    mask, lq = L.sphere_obstacle(16, 16, 16, (8.0, 8.0, 8.0), 4.5)
+    ph = lambda x, y, z: np.sqrt((x - 8.0) ** 2 + (y - 8.0) ** 2 + (z - 8.0) ** 2) - 4.5
+    along = lambda px, py, pz, c: (lambda t: ph(px + t * c[0], py + t * c[1], pz + t * c[2]))
+    lqb = L._link_fractions(along, mask.astype(bool), (16, 16, 16))
+    assert np.abs(lqb - lq).max() < 1e-8
+    n = 3 + 16 * (8 + 16 * 8)                 # node (3, 8, 8), link +x ends at (4, 8, 8) inside
+    assert mask[n] == 0 and mask[n + 1] == 1
+    assert abs(lq[2, 1, 1, n] - 0.5) < 1e-12  # the surface is at x = 3.5
+
+
+def test_tapered_posts_geometry():
+    nx = ny = 32
+    nz = 24
+    mask, lq = L.tapered_posts(nx, ny, nz, 2, 5.0, 2.0, 12.0, 16)
+    m3 = mask.reshape(nz, ny, nx).astype(bool)
+    assert m3[:2].all() and not m3[2:, 0, 0].any()          # floor only at the cell corners
+    assert m3[2, 8, 8] and m3[13, 8, 8] and not m3[14, 8, 8]   # post axis up to z = 1.5 + 12
+    # horizontal link towards the post axis at height z: the surface radius there is
+    # 5 - 3 (z - 1.5) / 12, so from x = 8 + d along -x the cut is at d - r
+    for z in (3, 7, 11):
+        r = 5.0 - 3.0 * (z - 1.5) / 12.0
+        d = int(np.floor(r)) + 1
+        n = (8 + d) + nx * (8 + ny * z)
+        assert mask[n] == 0 and mask[n - 1] == 1
+        assert abs(lq[0, 1, 1, n] - (d - r)) < 1e-8
+    # every floor link from the first fluid layer is cut halfway
+    n = 0 + nx * (0 + ny * 2)
+    assert abs(lq[1, 1, 0, n] - 0.5) < 1e-8 and abs(lq[0, 0, 0, n] - 0.5) < 1e-8
+    # and the ceiling (periodic z: the floor seen from the top layer)
+    n = 0 + nx * (0 + ny * (nz - 1))
+    assert abs(lq[1, 1, 2, n] - 0.5) < 1e-8
+    # only links from fluid into solid nodes carry a fraction, all in (0, 1]
+    assert lq.min() >= 0 and lq.max() <= 1
