@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2, drop-impact and posts legs")
+    ap.add_argument("--posts-only", action="store_true",
+                    help="run only the tapered-posts leg (curved walls) and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -288,6 +290,11 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.posts_only:
+        base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
+        a3 = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)
+        print(json.dumps({"d3q27_256_tapered_posts": tapered_posts_workload(P, torch, a3)}), flush=True)
+        return
     n = args.size
     N = n ** 3
     log(f"[bench] FP32 deviation-storage leg {n}^3 warmup={args.warmup} steps={args.steps}")

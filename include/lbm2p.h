@@ -170,6 +170,18 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]);
  * Returns LBM_E_DOMAIN when the EOS has no van der Waals loop at that temperature. */
 int lbm_coexistence(const lbm_params *p, double out[4]);
 
+/* Surface tension of the flat equilibrium interface of the second-gradient fluid
+ * (Sec. 2.1, Sec. 3.2) with the capillary coefficient p->kappa at the problem's
+ * temperature: sigma = integral kappa rho'^2 dx over the interface, evaluated as the
+ * integral over [rho_v, rho_l] of sqrt(2 kappa (Omega(rho) - Omega_sat)). Host only.
+ * Returns LBM_E_DOMAIN when the EOS has no van der Waals loop at that temperature. */
+int lbm_surface_tension(const lbm_params *p, double *sigma);
+
+/* Equation of state of the problem statement (Sec. 3.1; Shan-Chen as documented at
+ * LBM_EOS_SC1): P[k] = P(rho[k]) for k < n, host arrays (caller-owned). For pressure
+ * probes such as the Young-Laplace contact-angle measurement (Sec. 4.5). Host only. */
+int lbm_eos_pressure(const lbm_params *p, const double *rho, int64_t n, double *P);
+
 /* Capillary coefficient for which the flat equilibrium interface of the
  * second-gradient fluid (Sec. 2.1) has width W = (rho_l - rho_v)/max|grad rho|
  * (eq interface_W). Host only. */

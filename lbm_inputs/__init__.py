@@ -232,6 +232,20 @@ def tapered_posts(nx: int, ny: int, nz: int, floor: int, r_base: float, r_tip: f
     return solid.astype(np.uint8), _link_fractions(along, solid, (nx, ny, nz))
 
 
+def channel_column(nx: int, H: int, wall: int, rho_liquid: float, rho_vapour: float, width: float,
+                   x0: float, x1: float):
+    """D2Q9 channel along x between solid rows: `wall` solid rows at the bottom and at the
+    top, H fluid rows between them (ny = H + 2 wall), periodic in x. A liquid column fills
+    x0 <= x < x1 across the whole channel, with tanh faces of width `width`; vapour
+    elsewhere. Returns (mask uint8 [N], rho [N]); solid nodes carry rho_vapour."""
+    ny = H + 2 * wall
+    x, y, _ = _grid(nx, ny, 1)
+    d = np.minimum(x - x0, x1 - x)
+    rho = tanh_profile(d, rho_liquid, rho_vapour, width)
+    solid = (y < wall) | (y >= ny - wall)
+    return solid.astype(np.uint8), np.where(solid, rho_vapour, rho)
+
+
 def random_state(N: int, D: int, rho_lo: float, rho_hi: float, umax: float, seed: int):
     """Random density in [rho_lo, rho_hi) and velocity components in [-umax, umax)."""
     u01 = (splitmix64(seed, N) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)

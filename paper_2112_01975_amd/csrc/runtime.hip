@@ -415,6 +415,20 @@ int lbm_coexistence(const lbm_params *p, double out[4]) {
     return LBM_OK;
 }
 
+int lbm_surface_tension(const lbm_params *p, double *sigma) {
+    if (!p || !sigma || !(p->kappa >= 0)) return fail(nullptr, LBM_E_INVAL, "bad argument");
+    HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
+    if (surface_tension(e, p->kappa, sigma)) return fail(nullptr, LBM_E_DOMAIN, "no van der Waals loop at this temperature");
+    return LBM_OK;
+}
+
+int lbm_eos_pressure(const lbm_params *p, const double *rho, int64_t n, double *P) {
+    if (!p || (n > 0 && (!rho || !P)) || n < 0) return fail(nullptr, LBM_E_INVAL, "bad argument");
+    HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
+    for (int64_t k = 0; k < n; ++k) P[k] = e.P(rho[k]);
+    return LBM_OK;
+}
+
 int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa) {
     if (!p || !kappa || !(width > 0)) return fail(nullptr, LBM_E_INVAL, "bad argument");
     HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);

@@ -193,6 +193,30 @@ int coexistence(const HostEos &e, double *rv_out, double *rl_out, double *psat_o
     return 0;
 }
 
+int surface_tension(const HostEos &e, double kappa, double *sigma) {
+    double rv, rl, ps;
+    if (coexistence(e, &rv, &rl, &ps)) return -1;
+    // along the flat equilibrium profile kappa rho'^2 / 2 = Omega(rho) - Omega_sat, so
+    // sigma = integral_{rho_v}^{rho_l} sqrt(2 kappa (Omega - Omega_sat)) drho; the inner
+    // integral runs on from the previous node, the outer by Gauss panels in rho
+    const Gauss &G = gauss();
+    const int panels = 64;
+    const double hw = 0.5 * (rl - rv) / panels;
+    double acc = 0.0;
+    for (int k = 0; k < panels; ++k) {
+        const double mid = rv + (2 * k + 1) * hw;
+        double sub = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            const double r = mid + hw * G.x[q];
+            const double dom = r * integral_P_minus(e, ps, rv, r, 24);
+            sub += G.w[q] * sqrt(dom > 0.0 ? 2.0 * kappa * dom : 0.0);
+        }
+        acc += sub * hw;
+    }
+    *sigma = acc;
+    return 0;
+}
+
 int kappa_for_width(const HostEos &e, double width, double *kappa) {
     double rv, rl, ps;
     if (coexistence(e, &rv, &rl, &ps)) return -1;

@@ -19,5 +19,8 @@ struct HostEos {
 int coexistence(const HostEos &e, double *rho_v, double *rho_l, double *p_sat);
 // kappa giving interface width W = (rho_l - rho_v)/max|rho'| for the flat profile
 int kappa_for_width(const HostEos &e, double width, double *kappa);
+// surface tension of the flat interface of the second-gradient fluid with capillary
+// coefficient kappa: sigma = integral kappa rho'^2 dx = integral sqrt(2 kappa dOmega) drho
+int surface_tension(const HostEos &e, double kappa, double *sigma);
 
 }  // namespace lbm

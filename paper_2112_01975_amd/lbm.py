@@ -24,7 +24,8 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 EXPORTED = [
     "lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments", "lbm_destroy", "lbm_last_error",
     "lbm_set_stream", "lbm_population_bytes", "lbm_get_populations", "lbm_set_populations",
-    "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_batch_create",
+    "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_surface_tension",
+    "lbm_eos_pressure", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
     "lbm_batch_last_error",
 ]
@@ -76,6 +77,8 @@ def lib() -> C.CDLL:
         L.lbm_velocities.argtypes = [C.c_int, vp]
         L.lbm_coexistence.argtypes = [P, vp]
         L.lbm_kappa_for_width.argtypes = [P, d, C.POINTER(d)]
+        L.lbm_surface_tension.argtypes = [P, C.POINTER(d)]
+        L.lbm_eos_pressure.argtypes = [P, vp, i64, vp]
         L.lbm_batch_create.argtypes = [P, C.c_int, C.POINTER(vp)]
         L.lbm_batch_init_fields.argtypes = [vp, C.c_int, vp, vp]
         L.lbm_batch_step.argtypes = [vp, i64]
@@ -234,6 +237,21 @@ def lbm_kappa_for_width(p: Params, width: float) -> float:
     k = C.c_double()
     _check(lib().lbm_kappa_for_width(C.byref(cp), float(width), C.byref(k)), None)
     return k.value
+
+
+def lbm_surface_tension(p: Params) -> float:
+    cp = p.to_c()
+    s = C.c_double()
+    _check(lib().lbm_surface_tension(C.byref(cp), C.byref(s)), None)
+    return s.value
+
+
+def lbm_eos_pressure(p: Params, rho) -> np.ndarray:
+    cp = p.to_c()
+    r = np.ascontiguousarray(np.atleast_1d(rho), dtype=np.float64)
+    out = np.empty_like(r)
+    _check(lib().lbm_eos_pressure(C.byref(cp), _ptr(r), r.size, _ptr(out)), None)
+    return out
 
 
 def lbm_batch_create(cases: list[Params]):

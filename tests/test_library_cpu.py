@@ -42,6 +42,10 @@ def test_host_coexistence_matches_oracle(eos, a, om, tr):
     assert abs(Tt / (fl.G if eos in (T.SC1, T.SC2) else fl.T) - 1) < 1e-15
     k = P.lbm_kappa_for_width(p, 5.0)
     assert abs(k / T.kappa_for_width(fl, 5.0) - 1) < 1e-8
+    p.kappa = k
+    assert abs(P.lbm_surface_tension(p) / T.surface_tension(fl, k) - 1) < 1e-7
+    r = np.linspace(0.5 * ov, min(1.5 * ol, 0.99 * (fl.rho_max if hasattr(fl, "rho_max") else 1.5 * ol)), 7)
+    assert np.allclose(P.lbm_eos_pressure(p, r), [fl.pressure(x) for x in r], rtol=1e-13, atol=0)
 
 
 def test_no_loop_above_critical_temperature_is_a_domain_error():

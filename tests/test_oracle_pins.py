@@ -666,3 +666,40 @@ def test_tapered_posts_geometry():
     assert abs(lq[1, 1, 2, n] - 0.5) < 1e-8
     # only links from fluid into solid nodes carry a fraction, all in (0, 1]
     assert lq.min() >= 0 and lq.max() <= 1
+
+
+# ------------------------------------------------------------------ wetting (Sec. 4.5)
+def test_virtual_wall_density_spans_contact_angles_and_obeys_young_laplace():
+    # Liquid columns between walls of virtual density rho_w (vdW T/Tc = 0.7, W = 4, a
+    # channel of 24 fluid rows). The angle runs from 180 degrees at rho_w = rho_v to 0
+    # at rho_w = rho_l, decreasing in rho_w; in between, the angle of the fitted meniscus
+    # and the angle from the pressure jump through Laplace's law agree within 4 degrees.
+    # Laplace's law takes the model's own surface tension, measured on a free drop with
+    # the same parameters; it is 19% above the thermodynamic integral at this width.
+    from tests import wetting_analysis as WA
+    tr, W, H, nw, nx, steps = 0.7, 4.0, 24, 2, 72, 8000
+    fl0 = T.Fluid(T.VDW, A9, B21, tr)
+    a = A9 * 0.02 / T.kappa_for_width(fl0, W)
+    fl = T.Fluid(T.VDW, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    n = 48
+    cfg = O.Config(2, n, n, 1, T.VDW, a, B21, 1.0, 0.0, tr, 0.02, 0.8)
+    r, _, _ = O.Oracle(cfg).init(L.drop(n, n, 1, 12.0, rl, rv, W)).step(steps).moments()
+    r2 = r.reshape(n, n)
+    rin, rout = r2[n // 2, n // 2], r2[0, 0]
+    sigma_eff = (fl.pressure(rin) - fl.pressure(rout)) * T.equimolar_radius_2d(r, rout, rin)
+    assert 1.1 < sigma_eff / T.surface_tension(fl, 0.02) < 1.3
+    mask, rho0 = L.channel_column(nx, H, nw, rl, rv, W, nx / 3, 2 * nx / 3)
+    ny = H + 2 * nw
+    geo, yl = [], []
+    for frac in (0.0, 0.3, 0.5, 0.7, 1.0):
+        cfg = O.Config(2, nx, ny, 1, T.VDW, a, B21, 1.0, 0.0, tr, 0.02, 0.8, rho_wall=rv + frac * (rl - rv))
+        r, _, _ = O.Oracle(cfg, mask).init(rho0).step(steps).moments()
+        r2 = r.reshape(ny, nx)
+        geo.append(WA.geometric_angle(r2, nw, H, rl, rv))
+        yl.append(WA.young_laplace_angle(fl.pressure(r2[ny // 2, nx // 2]), fl.pressure(r2[ny // 2, 2]), sigma_eff, H))
+    assert geo[0] == 180.0 and yl[0] == 180.0          # rho_w = rho_v: non-wetting
+    assert geo[-1] == 0.0 and yl[-1] == 0.0            # rho_w = rho_l: complete wetting
+    assert geo[1] > geo[2] > geo[3] and 100 < geo[1] and geo[3] < 70
+    for g, y in zip(geo[1:4], yl[1:4]):
+        assert abs(g - y) < 4.0
