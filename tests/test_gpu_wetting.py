@@ -85,15 +85,17 @@ def test_calibration_in_the_h70_channel():
 def test_wettability_driven_column_matches_closed_form():
     import paper_2112_01975_amd as P
     from paper_2112_01975_amd import wetting as Wt
-    W, nu = 4.0, 0.075
+    from tests.golden_values import scalars
+    g = scalars("wettability_column")
+    W, nu = 4.0, g["nu"]
     base = _fluid(P, 0.7, W, 0.5 + 3 * nu)
     rv, rl, _, _ = P.lbm_coexistence(base)
     sigma = Wt.effective_surface_tension(base, radius=24.0, n=96, steps=20000)
     table = Wt.calibrate(base, [rv + f * (rl - rv) for f in (0.55, 0.6, 0.65, 0.7)], H=70, wall=2, nx=210,
                          steps=60000, sigma=sigma)
-    th_m, th_p = 59.3, 63.4
+    th_m, th_p = g["theta_minus"], g["theta_plus"]
     rw_m, rw_p = Wt.wall_density_for_angle(table, th_m), Wt.wall_density_for_angle(table, th_p)
-    H, Lx, Ll, nw = 70, 1260, 420, 2
+    H, Lx, Ll, nw = int(g["H"]), int(g["L"]), int(g["L_l"]), 2
     mask, rho0 = L.channel_column(Lx, H, nw, rl, rv, W, (Lx - Ll) / 2, (Lx + Ll) / 2)
     ny = H + 2 * nw
     p = replace(base, nx=Lx, ny=ny, mask=mask, rho_wall=rw_m)
