@@ -385,7 +385,8 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         C hh[27];
         const uint32_t lh = MM && halo ? links_at(sh, zs3) : 0u;
         const uint32_t bh = MM && halo ? qlo_at(sh, zs3) : 0u;
-        if (halo && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
+        // halo pulls of plane z+3 in flight during the stencil (FP32; REPULL pulls them below)
+        if (!REPULL && halo && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
         const uint32_t l3 = MM ? links_at(si, zs3) : 0u;
         const uint32_t b3 = MM && need3 ? qlo_at(si, zs3) : 0u;
 
@@ -393,7 +394,9 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         const bool act = own && z < g.nz &&
                          !(MASK && (plane_flags(z) & 1u) && ((fm.links[(si.v[1][1] + zoff) / SB] >> LINK_SELF) & 1u));
         if constexpr (REPULL) {
-            // plane z again: the loads are in flight during the stencil
+            // plane z again: the loads are in flight during the stencil (the halo node of
+            // plane z+3 is then pulled when it is staged, so that both sets of loads are
+            // never held at once: FP64 registers do not hold them)
             unsigned zsz[3];
             planes(z, zsz);
             if (act) {
@@ -434,6 +437,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         }
         if (halo) {
             C mh[4];
+            if (REPULL && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
             if constexpr (MM)
                 if (!((lh >> LINK_SELF) & 1u)) fix(Ab, lh, bh, sh, zs3, hh);
             stage(e_halo, (lh >> LINK_SELF) & 1u, (sh.v[1][1] + zs3[1]) / SB, hh, mh, slot, buf);
