@@ -9,13 +9,14 @@ namespace lbm {
 
 struct FusedGrid {
     int tx, ty, tz;        // tile width in x, height in y, planes per z-chunk
+    int zb, ze;            // the launch collides planes [zb, ze), in chunks of tz from zb
     int ntx, nty, nzc;     // tiles in x, y and z-chunks
     int items;             // ntx * nty * nzc work items
     int per_xcd;           // items per XCD (ceil(items / 8))
     int blocks;            // launched workgroups = 8 * per_xcd
 };
 
-FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz);
+FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze);
 
 // Solid geometry for the fused step (nullptr without solid nodes):
 //   links[n]  per-node solid-neighbour bits from fused_links;
@@ -30,6 +31,15 @@ struct FusedMask {
 
 using FusedLaunch = void (*)(hipStream_t, const void *A, void *B, const Geom &, const FusedMask &,
                              const void *params, const FusedGrid &);
+
+// One launch of a fused step: the kernel and the plane range it collides. A step is a
+// list of these over disjoint ranges that cover every plane: runs of planes within three
+// planes of a solid node take the masked kernel, the others the unmasked one (whose
+// registers are not shared with the bounce-back code).
+struct FusedSeg {
+    FusedLaunch fn;
+    FusedGrid fg;
+};
 
 // bit i of links[n]: the source node n - c_i of population i is solid; bit 27: n is solid
 void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom &g);

@@ -230,7 +230,8 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     const int rest = item / fg.ntx;
     const int tiy = rest % fg.nty;
     const int zc = rest / fg.nty;
-    const int x0 = tix * FTX, y0 = tiy * TY, z0 = zc * fg.tz;
+    const int x0 = tix * FTX, y0 = tiy * TY, z0 = fg.zb + zc * fg.tz;
+    const int tzi = min(fg.tz, fg.ze - z0);   // planes this item collides (the range's last chunk is ragged)
 
     using LT = std::conditional_t<SPLIT2, Lattice2<S>, Lattice1<S>>;   // two resources past 4 GiB
     const LT Ab(A, g.qs, false), Bb(B, g.qs, false);
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         unsigned zs3[3];
         planes(z + 3, zs3);
         const int slot = ((k + 5) % RING) * HP, buf = (k + 5) & 1;
-        const bool need3 = k + 1 < fg.tz;   // plane z+3 feeds the stencil of z+1
+        const bool need3 = k + 1 < tzi;   // plane z+3 feeds the stencil of z+1
         const bool halo = has_halo && need3;
         C hh[27];
         const uint32_t lh = MM && halo ? links_at(sh, zs3) : 0u;
@@ -525,17 +526,17 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     }
     if constexpr (REPULL) {
 #pragma unroll 1
-        for (int k = 0; k < fg.tz; k += 3) {
+        for (int k = 0; k < tzi; k += 3) {
             march(k, q0, m0);
-            if (k + 1 < fg.tz) march(k + 1, q0, m1);
-            if (k + 2 < fg.tz) march(k + 2, q0, m2);
+            if (k + 1 < tzi) march(k + 1, q0, m1);
+            if (k + 2 < tzi) march(k + 2, q0, m2);
         }
     } else {
 #pragma unroll 1
-        for (int k = 0; k < fg.tz; k += 3) {
+        for (int k = 0; k < tzi; k += 3) {
             march(k, q0, m0);
-            if (k + 1 < fg.tz) march(k + 1, q1, m1);
-            if (k + 2 < fg.tz) march(k + 2, q2, m2);
+            if (k + 1 < tzi) march(k + 1, q1, m1);
+            if (k + 2 < tzi) march(k + 2, q2, m2);
         }
     }
 }
@@ -590,14 +591,16 @@ void fused_qlo(hipStream_t s, const uint32_t *links, const void *lq, bool fp64, 
         hipLaunchKernelGGL(k_qlo<float>, dim3((g.N + 255) / 256), dim3(256), 0, s, links, (const float *)lq, qlo, g);
 }
 
-FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz) {
+FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze) {
     FusedGrid f;
     f.tx = tx;
     f.ty = ty;
     f.tz = tz;
+    f.zb = zb;
+    f.ze = ze;
     f.ntx = (g.nx + tx - 1) / tx;
     f.nty = (g.ny + ty - 1) / ty;
-    f.nzc = (g.nz + tz - 1) / tz;
+    f.nzc = (ze - zb + tz - 1) / tz;
     f.items = f.ntx * f.nty * f.nzc;
     f.per_xcd = (f.items + NXCD - 1) / NXCD;
     f.blocks = f.per_xcd * NXCD;

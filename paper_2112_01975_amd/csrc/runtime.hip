@@ -40,8 +40,8 @@ struct lbm_ctx {
     Params<double> pd{};
     Params<float> pf{};
     KernelSet ks{};
-    FusedLaunch fused = nullptr;     // single-pass step when available (D3Q27 FP32)
-    FusedGrid fg{};
+    FusedLaunch fused = nullptr;     // single-pass step when available (D3Q27): the first segment's kernel
+    std::vector<FusedSeg> segs;      // the launches of one fused step, over disjoint plane ranges
     bool initialized = false;
     int sticky = 0;
     double M0 = 0.0;
@@ -102,9 +102,14 @@ int watchdog(lbm_ctx *c) {
     return LBM_OK;
 }
 
+void fused_step(lbm_ctx *c) {
+    for (const FusedSeg &sg : c->segs)
+        sg.fn(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), sg.fg);
+}
+
 int one_step(lbm_ctx *c) {
     if (c->fused) {
-        c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), c->fg);
+        fused_step(c);
     } else {
         c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
@@ -157,17 +162,45 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
                 cus = n;
         }
         const long long tiles = (long long)((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty);
-        long long nzc = (cus + tiles - 1) / tiles;
-        nzc = std::min<long long>(nzc, std::max(1, (c->g.nz + 15) / 16));   // chunks of >= 16 planes
-        nzc = std::max<long long>(nzc, 1);
-        const int tz = env_int("LBM2P_FUSED_TZ", (int)((c->g.nz + nzc - 1) / nzc));
+        // chunk length for a run of len planes
+        auto chunk = [&](int len) {
+            long long nzc = (cus + tiles - 1) / tiles;
+            nzc = std::min<long long>(nzc, std::max(1, (len + 15) / 16));   // chunks of >= 16 planes
+            nzc = std::max<long long>(nzc, 1);
+            const int tz = env_int("LBM2P_FUSED_TZ", (int)((len + nzc - 1) / nzc));
+            return tz > 0 ? tz : 32;
+        };
         // the fused kernel addresses a lattice through one buffer resource, or through two
         // (populations 0-13 and 14-26) when it exceeds the 4 GiB reach of one
         const unsigned long long whole = 27ull * (unsigned long long)c->g.qs * c->sbytes;
         const unsigned long long part = 14ull * (unsigned long long)c->g.qs * c->sbytes;
         if (part < 0xFFFFFFFFull) {
-            c->fused = fused_launcher(c->fp64, c->masked, tx, ty, whole >= 0xFFFFFFFFull, p->link_q != nullptr);
-            if (c->fused) c->fg = fused_grid(c->g, tx, ty, tz > 0 ? tz : 32);
+            const bool split = whole >= 0xFFFFFFFFull;
+            const FusedLaunch plain = fused_launcher(c->fp64, false, tx, ty, split, false);
+            const FusedLaunch walls = c->masked ? fused_launcher(c->fp64, true, tx, ty, split, p->link_q != nullptr)
+                                                : nullptr;
+            const int nz = c->g.nz;
+            if (!c->masked) {
+                if (plain) c->segs.push_back({plain, fused_grid(c->g, tx, ty, chunk(nz), 0, nz)});
+            } else if (walls) {
+                // A plane is collided, staged and pulled from within three planes of itself,
+                // so planes with no solid node in z-3..z+3 run the unmasked kernel; maximal
+                // runs of equal kind become the launches of a step
+                const size_t nxy = (size_t)c->g.nx * c->g.ny;
+                std::vector<char> has(nz, 0), near(nz, 0);
+                for (int z = 0; z < nz; ++z)
+                    for (size_t q = 0; q < nxy && !has[z]; ++q) has[z] = p->mask[(size_t)z * nxy + q] ? 1 : 0;
+                for (int z = 0; z < nz; ++z)
+                    for (int d = -3; d <= 3 && !near[z]; ++d) near[z] = has[((z + d) % nz + nz) % nz];
+                for (int zb = 0; zb < nz;) {
+                    int ze = zb + 1;
+                    while (ze < nz && near[ze] == near[zb]) ++ze;
+                    const FusedLaunch fn = near[zb] || !plain ? walls : plain;
+                    c->segs.push_back({fn, fused_grid(c->g, tx, ty, chunk(ze - zb), zb, ze)});
+                    zb = ze;
+                }
+            }
+            if (!c->segs.empty()) c->fused = c->segs[0].fn;
         }
     }
     const size_t N = (size_t)c->g.N;
@@ -310,7 +343,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
             c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
         if (c->fused)
-            c->fused(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), c->fg);
+            fused_step(c);
         else
             c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
         HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));

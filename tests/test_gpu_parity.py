@@ -272,6 +272,34 @@ def test_fused_step_matches_two_pass_fp64(dims, masked, monkeypatch):
     assert abs(fused[2][0] / two[2][0] - 1) < 1e-14
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_step_plane_runs_match_two_pass(precision, monkeypatch):
+    # solids in two separate z-bands (a slab at z = 30..31 and scattered nodes at z = 5):
+    # the step becomes alternating runs of masked and unmasked launches, with ragged
+    # chunks inside the runs; it must agree with the two-pass step as the single-launch
+    # fused step does
+    nx, ny, nz = 40, 20, 64
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[30:32] = 1
+    m[30:32, 5:9, 10:14] = 0                       # a hole through the slab
+    m[5, 3, 7] = m[5, 12, 30] = 1
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6, rho_wall=0.0102306,
+                mask=m.ravel())
+    rv, rl = case.coexistence()
+    rho0 = L.drop(nx, ny, nz, 8.0, rl, rv, 5.0, centre=(20.0, 10.0, 16.0), noise=1e-5, seed=1011)
+    rho0 = np.where(m.ravel().astype(bool), rv, rho0)
+    rr = rv if precision else 0.0
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "10")
+    fused = run_gpu(case, rho0, None, 30, precision=precision, rho_ref=rr)
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    two = run_gpu(case, rho0, None, 30, precision=precision, rho_ref=rr)
+    assert np.all(np.isfinite(fused[0]))
+    if precision == 0:
+        assert max_rel(fused[0], two[0]) < 1e-12 and np.abs(fused[1] - two[1]).max() < 1e-13
+    else:
+        assert max_rel(fused[0], two[0]) < 1e-5 and np.abs(fused[1] - two[1]).max() < 1e-6
+
+
 # ---------------------------------------------------------------- batched sweep
 def _sweep_cases(n, steps_len_lo=32, steps_len_hi=96):
     """A reduced temperature sweep: D2Q9 4 x L flat interfaces, FP64 from T/Tc >= 0.95."""
