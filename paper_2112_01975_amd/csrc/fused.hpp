@@ -48,8 +48,10 @@ void fused_links(hipStream_t s, const uint8_t *mask, uint32_t *links, const Geom
 void fused_qlo(hipStream_t s, const uint32_t *links, const void *lq, bool fp64, uint32_t *qlo, const Geom &g);
 
 // nullptr when no fused variant exists for this combination
-// split: the lattice exceeds one buffer resource (4 GiB) and is addressed as two;
+// lat: how the kernel addresses a lattice: 0 one buffer resource (below 4 GiB), 1 two
+// buffer resources (populations 0-13 and 14-26, each below 4 GiB), 2 one resource per
+// group of four (FP32) or two (FP64) populations (population arrays below 1 GiB or 2 GiB);
 // interp: walls with per-link fractions (Params::link_q), interpolated bounce-back
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split, bool interp);
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, int lat, bool interp);
 
 }  // namespace lbm

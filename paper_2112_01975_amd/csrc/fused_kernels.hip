@@ -126,6 +126,45 @@ template <class S> struct Lattice2 {
     }
 };
 
+// One population lattice through K = ceil(27 / P) buffer resources of P populations each,
+// for lattices past the 8 GiB of two resources: population i is in resource i / P at
+// byte offset (i mod P) qs sizeof(S) + soff + voff, which stays below 4 GiB while P
+// population arrays do. The resource index is a compile-time constant at every access;
+// a bounce-back whose two populations sit in different resources loads both and keeps
+// one. A zero-extent view (null) returns 0 for every load without touching memory.
+template <class S, int P> struct LatticeK {
+    static constexpr int K = (27 + P - 1) / P;
+    __amdgpu_buffer_rsrc_t r[K];
+    unsigned qsb;
+    __device__ __forceinline__ LatticeK(const S *base, long long qs, bool null) : qsb((unsigned)(qs * (long long)sizeof(S))) {
+        static_for<0, K>([&](auto Kk) {
+            constexpr int k = decltype(Kk)::value;
+            constexpr int n = (k + 1) * P <= 27 ? P : 27 - k * P;
+            r[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base) + (long long)k * P * qs, (short)0,
+                                                     null ? 0 : (int)(unsigned)(n * qs * (long long)sizeof(S)),
+                                                     0x00020000);
+        });
+    }
+    template <int i> __device__ __forceinline__ S load(unsigned voff, unsigned soff) const {
+        return Lattice2<S>::raw_load(r[i / P], voff, soff + (unsigned)(i % P) * qsb);
+    }
+    template <int i> __device__ __forceinline__ S load_or_bounce(bool solid, unsigned voff, unsigned soff, unsigned vself,
+                                                               unsigned sself) const {
+        constexpr int o = opp<3>(i);
+        if constexpr (i / P == o / P) {
+            const unsigned off = solid ? vself + sself + (unsigned)(o % P) * qsb : voff + soff + (unsigned)(i % P) * qsb;
+            return Lattice2<S>::raw_load(r[i / P], off, 0u);
+        } else {
+            const S f = load<i>(voff, soff);
+            const S b = load<o>(vself, sself);
+            return solid ? b : f;
+        }
+    }
+    template <int i> __device__ __forceinline__ void store(unsigned voff, unsigned soff, S v) const {
+        Lattice2<S>::raw_store(r[i / P], voff, soff + (unsigned)(i % P) * qsb, v);
+    }
+};
+
 // Solid-neighbour bits of a node (built once per geometry by k_links): bit i is set
 // when the source node r - c_i of population i is solid, bit LINK_SELF when r is.
 constexpr int LINK_SELF = 27;
@@ -210,7 +249,7 @@ __device__ __forceinline__ void pull_all(const LT &A, uint32_t lm, const Stencil
     });
 }
 
-template <class S, class C, bool MASK, int FTX, int TY, bool REPULL, bool SPLIT2, bool INTERP>
+template <class S, class C, bool MASK, int FTX, int TY, bool REPULL, int LAT, bool INTERP>
 __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                       FusedMask fm, Params<C> p, FusedGrid fg) {
     constexpr int NT = FTX * TY;
@@ -233,7 +272,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     const int x0 = tix * FTX, y0 = tiy * TY, z0 = fg.zb + zc * fg.tz;
     const int tzi = min(fg.tz, fg.ze - z0);   // planes this item collides (the range's last chunk is ragged)
 
-    using LT = std::conditional_t<SPLIT2, Lattice2<S>, Lattice1<S>>;   // two resources past 4 GiB
+    // lattice view: one buffer resource (LAT 0), two past 4 GiB (1), and past 8 GiB groups
+    // of four (FP32) or two (FP64) populations per resource (2)
+    using LT = std::conditional_t<LAT == 2, LatticeK<S, sizeof(S) == 4 ? 4 : 2>,
+                                  std::conditional_t<LAT == 1, Lattice2<S>, Lattice1<S>>>;
     const LT Ab(A, g.qs, false), Bb(B, g.qs, false);
     // a zero-extent view of A: loads through it return 0 without touching memory
     const LT Anull(A, g.qs, true);
@@ -446,7 +488,9 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
 
         // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
         // loads go to Anull
-        const LT src = need3 ? Ab : Anull;
+        // (grouped resources: Ab itself, which reads wrapped planes never used, so that a
+        // second set of resources does not take scalar registers)
+        const LT src = (LAT == 2 || need3) ? Ab : Anull;
         if (act) {
             constexpr C W0 = C(1.0 / 6.0), W1 = C(2.0 / 3.0);
             const C drho = ma[0];
@@ -541,10 +585,10 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     }
 }
 
-template <class S, class C, bool MASK, int TX, int TY, bool REPULL, bool SPLIT2, bool INTERP = false>
+template <class S, class C, bool MASK, int TX, int TY, bool REPULL, int LAT, bool INTERP = false>
 void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const FusedMask &fm, const void *prm,
                   const FusedGrid &fg) {
-    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL, SPLIT2, INTERP>), dim3(fg.blocks), dim3(TX * TY), 0, s,
+    hipLaunchKernelGGL((k_fused3<S, C, MASK, TX, TY, REPULL, LAT, INTERP>), dim3(fg.blocks), dim3(TX * TY), 0, s,
                        (const S *)A, (S *)B, g, fm, *(const Params<C> *)prm, fg);
 }
 
@@ -609,26 +653,37 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze) {
 
 namespace {
 template <int TX, int TY> FusedLaunch pick(bool masked) {
-    return masked ? launch_fused<float, float, true, TX, TY, false, false>
-                  : launch_fused<float, float, false, TX, TY, false, false>;
+    return masked ? launch_fused<float, float, true, TX, TY, false, 0>
+                  : launch_fused<float, float, false, TX, TY, false, 0>;
 }
 }  // namespace
 
-FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, bool split, bool interp) {
+FusedLaunch fused_launcher(bool fp64, bool masked, int tx, int ty, int lat, bool interp) {
+    if (lat == 2) {   // grouped resources: 64 x 8 only
+        if (tx != 64 || ty != 8) return nullptr;
+        if (fp64)
+            return interp   ? (masked ? launch_fused<double, double, true, 64, 8, true, 2, true> : nullptr)
+                   : masked ? launch_fused<double, double, true, 64, 8, true, 2>
+                            : launch_fused<double, double, false, 64, 8, true, 2>;
+        return interp   ? (masked ? launch_fused<float, float, true, 64, 8, false, 2, true> : nullptr)
+               : masked ? launch_fused<float, float, true, 64, 8, false, 2>
+                        : launch_fused<float, float, false, 64, 8, false, 2>;
+    }
+    const bool split = lat == 1;
     if (interp) {   // interpolated walls: masked 64 x 8 variants only
         if (!masked || tx != 64 || ty != 8) return nullptr;
         if (fp64)
-            return split ? launch_fused<double, double, true, 64, 8, true, true, true>
-                         : launch_fused<double, double, true, 64, 8, true, false, true>;
-        return split ? nullptr : launch_fused<float, float, true, 64, 8, false, false, true>;
+            return split ? launch_fused<double, double, true, 64, 8, true, 1, true>
+                         : launch_fused<double, double, true, 64, 8, true, 0, true>;
+        return split ? nullptr : launch_fused<float, float, true, 64, 8, false, 0, true>;
     }
     if (fp64) {
         if (tx != 64 || ty != 8) return nullptr;
         if (split)
-            return masked ? launch_fused<double, double, true, 64, 8, true, true>
-                          : launch_fused<double, double, false, 64, 8, true, true>;
-        return masked ? launch_fused<double, double, true, 64, 8, true, false>
-                      : launch_fused<double, double, false, 64, 8, true, false>;
+            return masked ? launch_fused<double, double, true, 64, 8, true, 1>
+                          : launch_fused<double, double, false, 64, 8, true, 1>;
+        return masked ? launch_fused<double, double, true, 64, 8, true, 0>
+                      : launch_fused<double, double, false, 64, 8, true, 0>;
     }
     if (split) return nullptr;
     if (tx == 64 && ty == 8) return pick<64, 8>(masked);

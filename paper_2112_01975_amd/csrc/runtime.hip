@@ -162,22 +162,32 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
                 cus = n;
         }
         const long long tiles = (long long)((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty);
-        // chunk length for a run of len planes
+        // Chunk length for a run of len planes. Each work item (tile x chunk) marches its
+        // planes after a five-plane prologue; items run in rounds of one per CU. The number
+        // of chunks minimises rounds x (planes per chunk + 6), chunks of >= 16 planes: long
+        // chunks, but no last round that leaves most CUs idle (288 tiles on 256 CUs in one
+        // chunk would take two full rounds' time for 1.1 rounds' work).
         auto chunk = [&](int len) {
-            long long nzc = (cus + tiles - 1) / tiles;
-            nzc = std::min<long long>(nzc, std::max(1, (len + 15) / 16));   // chunks of >= 16 planes
-            nzc = std::max<long long>(nzc, 1);
-            const int tz = env_int("LBM2P_FUSED_TZ", (int)((len + nzc - 1) / nzc));
+            long long best = 1, cost = -1;
+            for (long long nzc = 1; nzc <= std::max(1, len / 16); ++nzc) {
+                const long long rounds = (tiles * nzc + cus - 1) / cus;
+                const long long c = rounds * ((len + nzc - 1) / nzc + 6);
+                if (cost < 0 || c < cost) { cost = c; best = nzc; }
+            }
+            const int tz = env_int("LBM2P_FUSED_TZ", (int)((len + best - 1) / best));
             return tz > 0 ? tz : 32;
         };
-        // the fused kernel addresses a lattice through one buffer resource, or through two
-        // (populations 0-13 and 14-26) when it exceeds the 4 GiB reach of one
-        const unsigned long long whole = 27ull * (unsigned long long)c->g.qs * c->sbytes;
-        const unsigned long long part = 14ull * (unsigned long long)c->g.qs * c->sbytes;
-        if (part < 0xFFFFFFFFull) {
-            const bool split = whole >= 0xFFFFFFFFull;
-            const FusedLaunch plain = fused_launcher(c->fp64, false, tx, ty, split, false);
-            const FusedLaunch walls = c->masked ? fused_launcher(c->fp64, true, tx, ty, split, p->link_q != nullptr)
+        // the fused kernel addresses a lattice through one buffer resource, through two
+        // (FP64, populations 0-13 and 14-26) when it exceeds the 4 GiB reach of one, and
+        // beyond that through one resource per group of four (FP32) or two (FP64)
+        // populations (LBM2P_FUSED_GROUPED=1 forces the last)
+        const unsigned long long pop = (unsigned long long)c->g.qs * c->sbytes;
+        int lat = 27 * pop < 0xFFFFFFFFull ? 0 : (c->fp64 && 14 * pop < 0xFFFFFFFFull ? 1 : 2);
+        if (env_int("LBM2P_FUSED_GROUPED", 0)) lat = 2;
+        if (lat == 2 && (c->fp64 ? 2 : 4) * pop >= 0xFFFFFFFFull) lat = -1;   // no fused step this large
+        if (lat >= 0) {
+            const FusedLaunch plain = fused_launcher(c->fp64, false, tx, ty, lat, false);
+            const FusedLaunch walls = c->masked ? fused_launcher(c->fp64, true, tx, ty, lat, p->link_q != nullptr)
                                                 : nullptr;
             const int nz = c->g.nz;
             if (!c->masked) {

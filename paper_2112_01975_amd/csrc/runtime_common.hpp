@@ -143,14 +143,16 @@ template <class C> inline C *upload_wall_field(const double *host, size_t N) {
 // (the population stride, so a kernel addresses them like a population array); nullptr
 // on failure
 template <class C> inline C *upload_link_q(const double *host, int Q, size_t N, long long qs) {
-    std::vector<C> tmp((size_t)Q * (size_t)qs, C(0));
-    for (int i = 0; i < Q; ++i)
-        for (size_t n = 0; n < N; ++n) tmp[(size_t)i * (size_t)qs + n] = C(host[(size_t)i * N + n]);
     C *d = nullptr;
-    if (hipMalloc((void **)&d, tmp.size() * sizeof(C)) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, tmp.data(), tmp.size() * sizeof(C), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        return nullptr;
+    if (hipMalloc((void **)&d, (size_t)Q * (size_t)qs * sizeof(C)) != hipSuccess) return nullptr;
+    std::vector<C> row((size_t)qs, C(0));   // one population at a time: host memory stays one row
+    for (int i = 0; i < Q; ++i) {
+        for (size_t n = 0; n < N; ++n) row[n] = C(host[(size_t)i * N + n]);
+        if (hipMemcpy(d + (size_t)i * (size_t)qs, row.data(), row.size() * sizeof(C), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            (void)hipFree(d);
+            return nullptr;
+        }
     }
     return d;
 }
