@@ -284,8 +284,8 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
             cd.mask = m;
         }
         if (p.rho_wall_field) {   // per-node wall densities of this case
-            void *w = cd.fp64 ? (void *)upload_wall_field<double>(p.rho_wall_field, N)
-                              : (void *)upload_wall_field<float>(p.rho_wall_field, N);
+            void *w = cd.fp64 ? (void *)upload_wall_field<double>(p.rho_wall_field, cd.g)
+                              : (void *)upload_wall_field<float>(p.rho_wall_field, cd.g);
             if (!w) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "wall density upload failed"); }
             b->allocs.push_back(w);
             if (cd.fp64) cd.pd.rho_wf = (const double *)w;

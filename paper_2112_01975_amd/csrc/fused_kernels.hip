@@ -283,11 +283,11 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     const int tx = t & (FTX - 1), ty = t / FTX;
     const int e_int = (ty + 2) * HX + tx + 2;
     const bool own = (x0 + tx < g.nx) && (y0 + ty < g.ny);
-    const int nxy = g.nx * g.ny;
+    const int nxy = g.px * g.ny;   // plane stride (rows pitched)
     auto stencil_of = [&](int x, int y, Stencil &st) __attribute__((always_inline)) {
         const int gx = wrapi(x, g.nx), gy = wrapi(y, g.ny);
         const int xs[3] = {wrapi(gx - 1, g.nx), gx, wrapi(gx + 1, g.nx)};
-        const int ry[3] = {g.nx * wrapi(gy - 1, g.ny), g.nx * gy, g.nx * wrapi(gy + 1, g.ny)};
+        const int ry[3] = {g.px * wrapi(gy - 1, g.ny), g.px * gy, g.px * wrapi(gy + 1, g.ny)};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -595,12 +595,16 @@ void launch_fused(hipStream_t s, const void *A, void *B, const Geom &g, const Fu
 __global__ void k_links(const uint8_t *__restrict__ mask, uint32_t *__restrict__ links, Geom g) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
-    const int x = n % g.nx, y = (n / g.nx) % g.ny, z = n / (g.nx * g.ny);
+    const int x = n % g.px, y = (n / g.px) % g.ny, z = n / (g.px * g.ny);
+    if (x >= g.nx) {   // row padding
+        links[n] = 0u;
+        return;
+    }
     uint32_t b = mask[n] ? (1u << LINK_SELF) : 0u;
     static_for<1, 27>([&](auto I) {
         constexpr int i = decltype(I)::value;
         const int s = wrapi(x - Lat<3>::c(i, 0), g.nx) +
-                      g.nx * (wrapi(y - Lat<3>::c(i, 1), g.ny) + g.ny * wrapi(z - Lat<3>::c(i, 2), g.nz));
+                      g.px * (wrapi(y - Lat<3>::c(i, 1), g.ny) + g.ny * wrapi(z - Lat<3>::c(i, 2), g.nz));
         if (mask[s]) b |= 1u << i;
     });
     links[n] = b;

@@ -7,9 +7,13 @@
 
 namespace lbm {
 
-// grid geometry; N < 2^31; qs = element stride between the Q population arrays
+// Grid geometry. Device arrays are pitched in x: node (x, y, z) is stored at
+// n = x + px (y + ny z) with px >= nx (rows padded to whole cache lines; the padding
+// nodes x >= nx are never read into real nodes nor written). N = px ny nz < 2^31 stored
+// nodes; qs = element stride between the Q population arrays.
 struct Geom {
     int nx, ny, nz;
+    int px;
     int N;
     long long qs;
 };

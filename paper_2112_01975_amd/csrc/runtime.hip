@@ -118,6 +118,18 @@ int one_step(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// nodes of the user layout (x fastest, rows of nx)
+size_t user_nodes(const lbm_ctx *c) { return (size_t)c->g.nx * c->g.ny * c->g.nz; }
+
+// Copy between the user layout (rows of nx elements) and the device layout (rows of px):
+// ny nz rows of nx elements of `elem` bytes, on the context stream.
+hipError_t copy_rows(lbm_ctx *c, void *dst, const void *src, size_t elem, hipMemcpyKind kind) {
+    const bool to_dev = kind == hipMemcpyHostToDevice;
+    const size_t upitch = (size_t)c->g.nx * elem, dpitch = (size_t)c->g.px * elem;
+    return hipMemcpy2DAsync(dst, to_dev ? dpitch : upitch, src, to_dev ? upitch : dpitch, upitch,
+                            (size_t)c->g.ny * c->g.nz, kind, c->stream);
+}
+
 int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
     return (v && *v) ? atoi(v) : dflt;
@@ -143,7 +155,17 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     c->fp64 = p->precision == LBM_FP64;
     c->masked = p->mask != nullptr;
     c->sbytes = c->fp64 ? 8 : 4;
-    c->g = make_geom(p->nx, p->ny, c->D == 3 ? p->nz : 1);
+    {
+        // rows padded to whole 128-byte lines (32 nodes) from nx = 64 on, so that a 64-node
+        // row load touches two cache lines, not three; LBM2P_PITCH_ALL=1 pads any nx
+        const int nx = p->nx, nz = c->D == 3 ? p->nz : 1;
+        const int px = (nx >= 64 || env_int("LBM2P_PITCH_ALL", 0)) ? (nx + 31) / 32 * 32 : nx;
+        if ((double)px * p->ny * nz >= 2147483647.0) {
+            delete c;
+            return fail(nullptr, LBM_E_INVAL, "grid larger than 2^31 nodes with its rows padded");
+        }
+        c->g = make_geom(nx, p->ny, nz, px);
+    }
     fill_params(p, &c->pd);
     fill_params(p, &c->pf);
     c->ks = kernel_set(c->D, c->fp64, c->masked);
@@ -231,8 +253,8 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         return fail(nullptr, LBM_E_NOMEM, "device allocation failed (" + std::to_string(2 * pop >> 20) + " MiB of populations)");
     }
     if (p->rho_wall_field) {   // per-node wall densities (solid entries are the ones used)
-        c->wall = c->fp64 ? (void *)upload_wall_field<double>(p->rho_wall_field, N)
-                          : (void *)upload_wall_field<float>(p->rho_wall_field, N);
+        c->wall = c->fp64 ? (void *)upload_wall_field<double>(p->rho_wall_field, c->g)
+                          : (void *)upload_wall_field<float>(p->rho_wall_field, c->g);
         if (!c->wall) {
             free_ctx(c);
             return fail(nullptr, LBM_E_NOMEM, "device allocation of the wall density field failed");
@@ -241,8 +263,8 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         else c->pf.rho_wf = (const float *)c->wall;
     }
     if (p->link_q) {   // wall fractions of the links into solid nodes
-        c->lq = c->fp64 ? (void *)upload_link_q<double>(p->link_q, c->Q, N, c->g.qs)
-                        : (void *)upload_link_q<float>(p->link_q, c->Q, N, c->g.qs);
+        c->lq = c->fp64 ? (void *)upload_link_q<double>(p->link_q, c->Q, c->g)
+                        : (void *)upload_link_q<float>(p->link_q, c->Q, c->g);
         if (!c->lq) {
             free_ctx(c);
             return fail(nullptr, LBM_E_NOMEM, "device allocation of the link fractions failed");
@@ -255,7 +277,8 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
             free_ctx(c);
             return fail(nullptr, LBM_E_NOMEM, "device allocation of the mask failed");
         }
-        if ((e = hipMemcpy(c->mask, p->mask, N, hipMemcpyHostToDevice)) != hipSuccess) {
+        const std::vector<uint8_t> mp = pitched<uint8_t>(p->mask, c->g);
+        if ((e = hipMemcpy(c->mask, mp.data(), N, hipMemcpyHostToDevice)) != hipSuccess) {
             free_ctx(c);
             return fail(nullptr, LBM_E_HIP, std::string("mask upload failed: ") + hipGetErrorString(e));
         }
@@ -298,12 +321,15 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
 
 int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u) {
     if (!c || !rho) return fail(c, LBM_E_INVAL, "context or rho is NULL");
-    const size_t N = (size_t)c->g.N;
-    for (size_t n = 0; n < N; ++n) {
+    const size_t N = (size_t)c->g.N, Nu = user_nodes(c);
+    for (size_t n = 0; n < Nu; ++n) {
         if (!(rho[n] > 0.0) || !isfinite(rho[n])) return fail(c, LBM_E_DOMAIN, "initial density must be finite and > 0");
     }
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->io, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    if (u) HIP_OR_FAIL(c, hipMemcpyAsync(c->io + N, u, (size_t)c->D * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, copy_rows(c, c->io, rho, sizeof(double), hipMemcpyHostToDevice));
+    if (u)
+        for (int a = 0; a < c->D; ++a)
+            HIP_OR_FAIL(c, copy_rows(c, c->io + N + (size_t)a * N, u + (size_t)a * Nu, sizeof(double),
+                                     hipMemcpyHostToDevice));
     const long long count = (long long)c->Q * c->g.qs;
     c->ks.fill_zero(c->stream, c->A, count);
     c->ks.fill_zero(c->stream, c->B, count);
@@ -391,8 +417,12 @@ int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]) {
         const size_t N = (size_t)c->g.N;
         c->ks.output(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->io, c->io + N);
         HIP_OR_FAIL(c, hipGetLastError());
-        if (rho) HIP_OR_FAIL(c, hipMemcpyAsync(rho, c->io, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        if (U) HIP_OR_FAIL(c, hipMemcpyAsync(U, c->io + N, (size_t)c->D * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        const size_t Nu = user_nodes(c);
+        if (rho) HIP_OR_FAIL(c, copy_rows(c, rho, c->io, sizeof(double), hipMemcpyDeviceToHost));
+        if (U)
+            for (int a = 0; a < c->D; ++a)
+                HIP_OR_FAIL(c, copy_rows(c, U + (size_t)a * Nu, c->io + N + (size_t)a * N, sizeof(double),
+                                         hipMemcpyDeviceToHost));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     }
     return LBM_OK;
@@ -414,26 +444,26 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream) {
 }
 
 int64_t lbm_population_bytes(const lbm_ctx *c) {
-    return c ? (int64_t)c->Q * (int64_t)c->g.N * (int64_t)c->sbytes : 0;
+    return c ? (int64_t)c->Q * (int64_t)user_nodes(c) * (int64_t)c->sbytes : 0;
 }
 
 int lbm_get_populations(lbm_ctx *c, void *host) {
     if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
     if (!c->initialized) return fail(c, LBM_E_STATE, "no state to checkpoint");
-    const size_t row = (size_t)c->g.N * c->sbytes;
+    const size_t row = user_nodes(c) * c->sbytes;
     for (int i = 0; i < c->Q; ++i)
-        HIP_OR_FAIL(c, hipMemcpyAsync((char *)host + i * row, (char *)c->A + (size_t)i * c->g.qs * c->sbytes, row,
-                                      hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, copy_rows(c, (char *)host + i * row, (char *)c->A + (size_t)i * c->g.qs * c->sbytes, c->sbytes,
+                                 hipMemcpyDeviceToHost));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
 int lbm_set_populations(lbm_ctx *c, const void *host) {
     if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
-    const size_t row = (size_t)c->g.N * c->sbytes;
+    const size_t row = user_nodes(c) * c->sbytes;
     for (int i = 0; i < c->Q; ++i)
-        HIP_OR_FAIL(c, hipMemcpyAsync((char *)c->A + (size_t)i * c->g.qs * c->sbytes, (const char *)host + i * row, row,
-                                      hipMemcpyHostToDevice, c->stream));
+        HIP_OR_FAIL(c, copy_rows(c, (char *)c->A + (size_t)i * c->g.qs * c->sbytes, (const char *)host + i * row,
+                                 c->sbytes, hipMemcpyHostToDevice));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->sticky = 0;

@@ -14,12 +14,13 @@ namespace lbm {
 
 // Element stride between population arrays: N rounded up to a 256 B multiple plus
 // a 768 B (FP32) skew so that the Q arrays do not start on the same HBM channel.
-inline Geom make_geom(int nx, int ny, int nz) {
+inline Geom make_geom(int nx, int ny, int nz, int px = 0) {
     Geom g;
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
-    g.N = nx * ny * nz;
+    g.px = px > nx ? px : nx;
+    g.N = g.px * ny * nz;
     g.qs = (((long long)g.N + 63) / 64) * 64 + 192;
     return g;
 }
@@ -125,11 +126,21 @@ template <class C> inline void fill_params(const lbm_params *p, Params<C> *q) {
     q->link_q = nullptr;   // likewise the link fractions
 }
 
+// Pitched copy of a host array in the user layout (x fastest, rows of nx): element (x, y, z)
+// at x + g.px (y + g.ny z); padding entries are zero.
+template <class C, class H> inline std::vector<C> pitched(const H *host, const Geom &g) {
+    std::vector<C> out((size_t)g.N, C(0));
+    const size_t rows = (size_t)g.ny * g.nz;
+    for (size_t r = 0; r < rows; ++r)
+        for (int x = 0; x < g.nx; ++x) out[r * g.px + x] = C(host[r * g.nx + x]);
+    return out;
+}
+
 // device copy of a per-node wall density field in compute precision C (solid entries
-// used; fluid entries copied as given); nullptr on failure
-template <class C> inline C *upload_wall_field(const double *host, size_t N) {
-    std::vector<C> tmp(N);
-    for (size_t n = 0; n < N; ++n) tmp[n] = C(host[n]);
+// used; fluid entries copied as given), pitched; nullptr on failure
+template <class C> inline C *upload_wall_field(const double *host, const Geom &g) {
+    const std::vector<C> tmp = pitched<C>(host, g);
+    const size_t N = tmp.size();
     C *d = nullptr;
     if (hipMalloc((void **)&d, N * sizeof(C)) != hipSuccess) return nullptr;
     if (hipMemcpy(d, tmp.data(), N * sizeof(C), hipMemcpyHostToDevice) != hipSuccess) {
@@ -139,15 +150,18 @@ template <class C> inline C *upload_wall_field(const double *host, size_t N) {
     return d;
 }
 
-// device copy of the wall fractions, [Q][N] host doubles -> [Q][qs] in compute precision
-// (the population stride, so a kernel addresses them like a population array); nullptr
-// on failure
-template <class C> inline C *upload_link_q(const double *host, int Q, size_t N, long long qs) {
+// device copy of the wall fractions, [Q][nx ny nz] host doubles -> [Q][qs] pitched in
+// compute precision (the population layout, so a kernel addresses them like a population
+// array); nullptr on failure
+template <class C> inline C *upload_link_q(const double *host, int Q, const Geom &g) {
+    const long long qs = g.qs;
+    const size_t Nu = (size_t)g.nx * g.ny * g.nz, rows = (size_t)g.ny * g.nz;
     C *d = nullptr;
     if (hipMalloc((void **)&d, (size_t)Q * (size_t)qs * sizeof(C)) != hipSuccess) return nullptr;
     std::vector<C> row((size_t)qs, C(0));   // one population at a time: host memory stays one row
     for (int i = 0; i < Q; ++i) {
-        for (size_t n = 0; n < N; ++n) row[n] = C(host[(size_t)i * N + n]);
+        for (size_t r = 0; r < rows; ++r)
+            for (int x = 0; x < g.nx; ++x) row[r * g.px + x] = C(host[(size_t)i * Nu + r * g.nx + x]);
         if (hipMemcpy(d + (size_t)i * (size_t)qs, row.data(), row.size() * sizeof(C), hipMemcpyHostToDevice) !=
             hipSuccess) {
             (void)hipFree(d);

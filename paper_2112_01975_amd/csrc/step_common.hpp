@@ -41,12 +41,12 @@ template <int D> struct Nbr {
 #pragma unroll
             for (int j = 0; j < 3; ++j)
 #pragma unroll
-                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * (ys[j] + g.ny * zs[l]);
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.px * (ys[j] + g.ny * zs[l]);
         } else {
 #pragma unroll
             for (int j = 0; j < 3; ++j)
 #pragma unroll
-                for (int l = 0; l < 3; ++l) ro[j][l] = g.nx * ys[j];
+                for (int l = 0; l < 3; ++l) ro[j][l] = g.px * ys[j];
         }
     }
     // from per-axis wrapped coordinates already multiplied out: xs = x-1, x, x+1;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g
     const int x = blockIdx.x * TX + tx, y = blockIdx.y * TY + ty, z = blockIdx.z;
     double v[kPartialSlots] = {0, 0, 0, 0, 0};
     if (x < g.nx && y < g.ny) {
-        const int n = x + g.nx * (y + g.ny * z);
+        const int n = x + g.px * (y + g.ny * z);
         C rho, ga[3] = {C(0), C(0), C(0)};
         if (MASK && mask[n]) {
             rho = wall_density(p, n);
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
         const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
         const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
-        const C r = rho_f[gx + g.nx * (gy + g.ny * gz)];
+        const C r = rho_f[gx + g.px * (gy + g.ny * gz)];
         s_rho[e] = r;
         s_psi[e] = signed_psi(p.eos, r);
     }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
     for (int zz = 0; zz < T::ZB; ++zz) {
         const int z = z0 + zz;
         if (z >= g.nz) break;
-        const int n = x + g.nx * (y + g.ny * z);
+        const int n = x + g.px * (y + g.ny * z);
         if (MASK && mask[n]) {
             if constexpr (OUT) {
                 out_rho[n] = double(wall_density(p, n));
@@ -247,8 +247,9 @@ template <int D, class S, class C>
 __global__ __launch_bounds__(256) void k_wall_init(S *__restrict__ A, Geom g, const uint8_t *__restrict__ mask,
                                                    const C *__restrict__ lq) {
     const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= g.N || mask[n]) return;
-    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+    if (n >= g.N) return;
+    const int x = n % g.px, t = n / g.px, y = t % g.ny, z = t / g.ny;
+    if (x >= g.nx || mask[n]) return;   // row padding, or solid
     Nbr<D> nb(g, x, y, z);
     constexpr int Q = Lat<D>::Q;
     C P[Q], X[Q];
