@@ -157,6 +157,38 @@ class BruteForce:
             self.f = fnew
         return self
 
+    def pressure_tensor(self):
+        """Discrete pressure tensor of Appendix E on the whole grid, components xx, yy, [zz,]
+        xy[, xz, yz] as a (D(D+1)/2, N) array: the lattice momentum flux of the pre-collision
+        populations minus the four non-local parts (force = minus their divergence, momentum
+        source = minus the force); zero at solid nodes."""
+        D = self.D
+        rho, _, _ = self.fields()
+        P = self.fluid.pressure(rho)
+        psi = np.sqrt(np.abs(P - rho / 3.0))
+        sgn = np.where(P > rho / 3.0, 1.0, -1.0)
+        pairs = [(0, 0), (1, 1), (0, 1)] if D == 2 else [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+        out = []
+        for a, b in pairs:
+            flux = np.zeros(self.shape)
+            ring1 = np.zeros(self.shape); ring2 = np.zeros(self.shape); across = np.zeros(self.shape)
+            cap1 = np.zeros(self.shape); cap2 = np.zeros(self.shape); capx = np.zeros(self.shape)
+            for c in self.vel:
+                weight = 3.0 * np.prod([AXIS_W[ci + 1] for ci in c]) * c[a] * c[b]
+                flux = flux + c[a] * c[b] * self.f[self._idx(c)]
+                if weight == 0.0:
+                    continue
+                ring1 += weight * _roll(psi, c, 1)
+                ring2 += weight * _roll(psi, c, 2)
+                across += weight * _roll(psi, c, -1) * _roll(psi, c, 1)
+                cap1 += weight * _roll(rho, c, 1)
+                cap2 += weight * _roll(rho, c, 2)
+                capx += weight * _roll(rho, c, -1) * _roll(rho, c, 1)
+            nonlocal_ = (-sgn * (8.0 / 6.0) * psi * ring1 + sgn / 6.0 * (psi * ring2 + across)
+                         - self.kappa * rho * cap1 + 0.5 * self.kappa * (rho * cap2 + capx))
+            out.append(np.where(self.solid, 0.0, flux - nonlocal_).ravel())
+        return np.stack(out)
+
     def moments(self):
         rho, u, S = self.fields()
         U = np.where(self.solid[None], 0.0, u + S / (2.0 * rho))

@@ -29,7 +29,8 @@
  *      population of its own node (halfway bounce-back), or, with per-link wall
  *      distances, by the linearly interpolated bounce-back of Bouzidi et al. that the
  *      paper uses for curved walls (Sec. 4.5, Sec. 5.3).
- * Output velocity U = u + S/(2 rho) (Sec. 2.3.5, Appendix D).
+ * Output velocity U = u + S/(2 rho) (Sec. 2.3.5, Appendix D). The discrete pressure tensor
+ * of a state (Appendix E) is orc_pressure_tensor.
  */
 #include <math.h>
 #include <stdint.h>
@@ -534,6 +535,61 @@ void orc_korteweg_force(void *h, const double *rho, double *F)
         }
         for (int a = 0; a < 3; ++a)
             F[a * N + n] = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * rho[n] * Fc[a];
+    }
+}
+
+/* Discrete pressure tensor of the current state (Appendix E), [D(D+1)/2][N] in the order
+ * xx, yy, [zz,] xy[, xz, yz]; zero at solid nodes. Appendix E writes the discrete force as
+ * the sum of four parts (one- and two-ring pseudo-potential and capillary terms) and gives
+ * each part's tensor, with the force the negative divergence of the tensor. With the
+ * reading S = -F of the momentum source, the momentum flux that the tensors complete is
+ * P = Pi - (P^A + P^B + P^C + P^D), where Pi_ab = sum_i c_ia c_ib f_i is the second moment of
+ * the node's pre-collision populations (the lattice momentum flux; rho/3 only without a
+ * force). Per node, with 3 w_i = w_i / cs^2 and s the sign of P - P0:
+ *   P^A = -s (8/6) psi(r) sum 3w c c psi(r + c)
+ *   P^B = +s (1/6) [psi(r) sum 3w c c psi(r + 2c) + sum 3w c c psi(r - c) psi(r + c)]
+ *   P^C = -kappa rho(r) sum 3w c c rho(r + c)
+ *   P^D = (kappa/2) [rho(r) sum 3w c c rho(r + 2c) + sum 3w c c rho(r - c) rho(r + c)]
+ * Solid nodes enter psi and rho with the wall density, as in the force. */
+void orc_pressure_tensor(void *h, double *out)
+{
+    orc_ctx *x = (orc_ctx *)h;
+    long N = x->N;
+    int D = x->D, Q = x->Q;
+    const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+    const int ncomp = D == 3 ? 6 : 3;
+    int comp[6][2];
+    for (int k = 0; k < ncomp; ++k) {
+        int kk = D == 3 ? k : (k < 2 ? k : 3);   /* D2Q9: xx, yy, xy */
+        comp[k][0] = pa[kk];
+        comp[k][1] = pb[kk];
+    }
+    fields(x);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        for (int k = 0; k < ncomp; ++k) {
+            if (solid(x, n)) { out[k * N + n] = 0.0; continue; }
+            const int a = comp[k][0], b = comp[k][1];
+            double pi = 0.0, sA = 0.0, sB1 = 0.0, sB2 = 0.0, sC = 0.0, sD1 = 0.0, sD2 = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                const double cc = 3.0 * x->w[i] * x->c[i][a] * x->c[i][b];
+                pi += x->c[i][a] * x->c[i][b] * x->f[i * N + n];
+                if (cc == 0.0) continue;
+                long p1 = nbr(x, n, 1, x->c[i]), p2 = nbr(x, n, 2, x->c[i]), m1 = nbr(x, n, -1, x->c[i]);
+                sA += cc * x->psi[p1];
+                sB1 += cc * x->psi[p2];
+                sB2 += cc * x->psi[m1] * x->psi[p1];
+                sC += cc * x->rho[p1];
+                sD1 += cc * x->rho[p2];
+                sD2 += cc * x->rho[m1] * x->rho[p1];
+            }
+            const double s = x->sgn[n], psi = x->psi[n], r = x->rho[n], kap = x->p.kappa;
+            const double PA = -s * (8.0 / 6.0) * psi * sA;
+            const double PB = s * (1.0 / 6.0) * (psi * sB1 + sB2);
+            const double PC = -kap * r * sC;
+            const double PD = 0.5 * kap * (r * sD1 + sD2);
+            out[k * N + n] = pi - (PA + PB + PC + PD);
+        }
     }
 }
 

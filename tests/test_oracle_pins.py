@@ -752,3 +752,82 @@ def test_virtual_wall_density_spans_contact_angles_and_obeys_young_laplace():
     assert geo[1] > geo[2] > geo[3] and 100 < geo[1] and geo[3] < 70
     for g, y in zip(geo[1:4], yl[1:4]):
         assert abs(g - y) < 4.0
+
+
+# ------------------------------------------------------------------ discrete pressure tensor (Appendix E)
+@pytest.mark.parametrize("D", [2, 3])
+def test_pressure_tensor_matches_numpy_twin(D):
+    nz, ny, nx = (1, 8, 7) if D == 2 else (4, 6, 5)
+    N = nx * ny * nz
+    fl = T.Fluid(T.VDW, 0.02, B21, 0.7)
+    rv, rl, _ = T.coexistence(fl)
+    rho, u = L.random_state(N, D, rv, rl, 0.05, 12)
+    mask = L.random_mask(nx, ny, nz, 0.2, 4)
+    cfg = O.Config(D, nx, ny, nz, T.VDW, 0.02, B21, 1.0, 0.0, 0.7, 0.02, 0.8, rho_wall=rv)
+    P1 = O.Oracle(cfg, mask).init(rho, u).step(3).pressure_tensor()
+    shape = (ny, nx) if D == 2 else (nz, ny, nx)
+    P2 = B.BruteForce(D, shape, fl, 0.02, 0.8, rho_wall=rv, mask=mask).init(rho, u).step(3).pressure_tensor()
+    assert np.abs(P1 - P2).max() < 1e-13 * np.abs(P2).max()
+
+
+@pytest.mark.parametrize("eos,a,om,tr", [(T.VDW, 0.02, 0.0, 0.7), (T.PR, 0.005046, 0.344, 0.6), (T.CS, 0.01, 0.0, 0.7)])
+def test_pressure_tensor_of_a_uniform_state_is_the_eos_pressure(eos, a, om, tr):
+    # at rest and uniform, the momentum flux is rho/3 and the four non-local parts add up to
+    # -(P - rho/3): the tensor is P(rho) times the identity, whichever side of P0 rho lies
+    fl = T.Fluid(eos, a, B21, tr, 1.0, om)
+    rv, rl, _ = T.coexistence(fl)
+    for rho0 in (rv, rl, 0.5 * (rv + rl)):
+        cfg = O.Config(3, 4, 3, 5, eos, a, B21, 1.0, om, tr, 0.02, 0.8)
+        Pt = O.Oracle(cfg).init(np.full(60, rho0)).pressure_tensor()
+        p = fl.pressure(rho0)
+        assert np.abs(Pt[:3] - p).max() < 1e-13 * max(abs(p), rho0 / 3)
+        assert np.abs(Pt[3:]).max() < 1e-15
+
+
+def _flat_interface_tensor(D, tr, W, steps):
+    fl0 = T.Fluid(T.VDW, A9, B21, tr)
+    a = A9 * 0.02 / T.kappa_for_width(fl0, W)
+    fl = T.Fluid(T.VDW, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    n = 64
+    ny, nz = (1, 1) if D == 2 else (2, 2)
+    cfg = O.Config(D, n, ny, nz, T.VDW, a, B21, 1.0, 0.0, tr, 0.02, 0.8)
+    o = O.Oracle(cfg).init(L.flat_slab(n, ny, nz, rl, rv, W)).step(steps)
+    r, _, _ = o.moments()
+    c, _, _ = O.lattice(D)
+    flux_xx = (c[:, 0:1].astype(float) ** 2 * o.populations()).sum(0)
+    return o.pressure_tensor(), r, flux_xx, fl, a
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_flat_interface_normal_pressure_is_uniform(D):
+    # Appendix E: across a flat interface at rest the discrete normal pressure is uniform and
+    # equals the bulk pressure on both sides (the continuous Korteweg form is not). Readings
+    # checked here: the non-local tensors enter with the sign of the momentum source
+    # S = -F (as printed, the bulk value would be 2 rho/3 - P), and the kinetic part is the
+    # lattice momentum flux (with rho/3 in its place the normal pressure varies by 40%)
+    Pt, r, flux, fl, _ = _flat_interface_tensor(D, 0.8, 4.0, 30000)
+    Pxx = Pt[0]
+    pb = fl.pressure(r[0])                                              # the vapour bulk
+    assert np.ptp(Pxx) < 1e-6 * pb                                      # uniform
+    assert abs(Pxx.mean() / pb - 1) < 1e-4                              # at the bulk pressure
+    nonlocal_ = flux - Pxx
+    assert (np.ptp(r / 3 - nonlocal_) / pb) > 0.2
+    assert abs((r[0] / 3 + nonlocal_[0]) / pb - 1) > 1.0
+
+
+def test_kirkwood_buff_tension_equals_laplace_tension():
+    # two independent measures of the model's surface tension: the integral of P_xx - P_yy
+    # across the flat interfaces (Kirkwood-Buff, with the discrete tensor) and Laplace's
+    # law on a free drop with the same parameters (vdW T/Tc = 0.7, W = 4)
+    Pt, r, _, fl, a = _flat_interface_tensor(2, 0.7, 4.0, 40000)
+    sigma_kb = float(np.sum(Pt[0] - Pt[1])) / 2                        # the slab has two interfaces
+    rv, rl, _ = T.coexistence(fl)
+    n = 48
+    cfg = O.Config(2, n, n, 1, T.VDW, a, B21, 1.0, 0.0, 0.7, 0.02, 0.8)
+    rd, _, _ = O.Oracle(cfg).init(L.drop(n, n, 1, 12.0, rl, rv, 4.0)).step(8000).moments()
+    r2 = rd.reshape(n, n)
+    rin, rout = r2[n // 2, n // 2], r2[0, 0]
+    sigma_lap = (fl.pressure(rin) - fl.pressure(rout)) * T.equimolar_radius_2d(rd, rout, rin)
+    assert abs(sigma_kb / sigma_lap - 1) < 0.02
+    assert 1.1 < sigma_kb / T.surface_tension(fl, 0.02) < 1.3
