@@ -129,6 +129,20 @@ int lbm_step(lbm_ctx *c, int64_t n);
  * Synchronous. */
 int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]);
 
+/* Discrete pressure tensor of the current state (Appendix E). P: host [D(D+1)/2][N]
+ * (caller-owned), components xx, yy, xy for D2Q9 and xx, yy, zz, xy, xz, yz for D3Q27; zero
+ * at solid nodes. Appendix E splits the discrete Korteweg force into one- and two-ring
+ * pseudo-potential and capillary parts and gives each part's tensor (the force being its
+ * negative divergence). With the momentum source S = -F these tensors enter with a minus
+ * sign, and the kinetic part is the lattice momentum flux sum_i c_i c_i f_i of the
+ * pre-collision populations:
+ *   P = sum_i c_i c_i f_i - (P^A + P^B + P^C + P^D).
+ * At rest it is uniform in the normal direction across flat interfaces and reduces to the
+ * EOS pressure in uniform regions; the integral of P_nn - P_tt across an interface is the
+ * surface tension (Kirkwood-Buff, Sec. 3.2). Synchronous; the first call allocates
+ * D(D+1)/2 N doubles of device memory kept until lbm_destroy. */
+int lbm_pressure_tensor(lbm_ctx *c, double *P);
+
 /* Releases all device memory and the stream. NULL-safe. */
 void lbm_destroy(lbm_ctx *c);
 

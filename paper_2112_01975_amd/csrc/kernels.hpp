@@ -55,6 +55,10 @@ struct KernelSet {
     // rho and U = u + S/(2 rho) of the current state in FP64 (reads rho, g)
     void (*output)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
                    const void *rho, const void *g, double *out_rho, double *out_U);
+    // discrete pressure tensor of the state in A (reads rho written by moments), FP64
+    // [D(D+1)/2][N] into out
+    void (*pressure)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
+                     const void *rho, double *out);
     int moment_blocks;  // filled by kernel_blocks()
 };
 

@@ -36,6 +36,7 @@ struct lbm_ctx {
     void *lq = nullptr;              // per-link wall fractions in compute precision (optional)
     double *partials = nullptr, *totals = nullptr;
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
+    double *ptens = nullptr;         // FP64 pressure tensor output, D(D+1)/2 * N (on first use)
     int nblk = 0;
     Params<double> pd{};
     Params<float> pf{};
@@ -69,7 +70,7 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
     void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->qlo, c->wall, c->lq, c->partials,
-                    c->totals, c->io};
+                    c->totals, c->io, c->ptens};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -425,6 +426,26 @@ int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]) {
                                          hipMemcpyDeviceToHost));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     }
+    return LBM_OK;
+}
+
+int lbm_pressure_tensor(lbm_ctx *c, double *P) {
+    if (!c || !P) return fail(c, LBM_E_INVAL, "NULL argument");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_pressure_tensor before lbm_init_fields");
+    const int nc = c->D * (c->D + 1) / 2;
+    const size_t N = (size_t)c->g.N, Nu = user_nodes(c);
+    if (!c->ptens && hipMalloc((void **)&c->ptens, (size_t)nc * N * sizeof(double)) != hipSuccess) {
+        c->ptens = nullptr;
+        return fail(c, LBM_E_NOMEM, "device allocation of the pressure tensor failed");
+    }
+    double t[5];
+    int rc = reduce_state(c, t);    // rho of the current state
+    if (rc) return rc;
+    c->ks.pressure(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->ptens);
+    HIP_OR_FAIL(c, hipGetLastError());
+    for (int k = 0; k < nc; ++k)
+        HIP_OR_FAIL(c, copy_rows(c, P + (size_t)k * Nu, c->ptens + (size_t)k * N, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 

@@ -100,12 +100,17 @@ template <int D> struct Tile {
     static constexpr int LS = LX * LY * LZ;
 };
 
-enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2 };
+enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2, MODE_PT = 3 };
 
 // MODE_STEP: one collide-stream step A -> B.
 // MODE_OUT:  rho and U = u + S/(2 rho) of the state in A, FP64, into out_rho / out_U.
 // MODE_INIT: equilibrium of the density in rho_f and the flow velocity U0 (= out_U, may be
 //            NULL): bare u = U0 - S/(2 rho), written into B in pull layout.
+// MODE_PT:   discrete pressure tensor of the state in A (Appendix E) into out_U, FP64
+//            [D(D+1)/2][N]: xx, yy, [zz,] xy[, xz, yz]; zero at solid nodes. The lattice
+//            momentum flux of the pulled (pre-collision) populations minus the one- and
+//            two-ring pseudo-potential and capillary tensors, which enter with the sign of
+//            the momentum source S = -F.
 template <int D, class S, class C, bool MASK, int MODE>
 __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                  const uint8_t *__restrict__ mask, Params<C> p,
@@ -137,6 +142,52 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             if constexpr (OUT) {
                 out_rho[n] = double(wall_density(p, n));
                 for (int a = 0; a < D; ++a) out_U[(long long)a * g.N + n] = 0.0;
+            }
+            if constexpr (MODE == MODE_PT)
+                for (int k = 0; k < D * (D + 1) / 2; ++k) out_U[(long long)k * g.N + n] = 0.0;
+            continue;
+        }
+        const int lc0 = ((D == 3 ? zz + HALO : 0) * T::LY + ty + HALO) * T::LX + tx + HALO;
+        if constexpr (MODE == MODE_PT) {
+            Nbr<D> nb(g, x, y, z);
+            C h[Lat<D>::Q];
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h, p.link_q);
+            constexpr int NC = D * (D + 1) / 2;
+            constexpr int ca[6] = {0, 1, D == 3 ? 2 : 0, 0, 0, 1}, cb[6] = {0, 1, D == 3 ? 2 : 1, 1, 2, 2};
+            C flux[NC], ringA[NC], ringB[NC], across[NC], cap1[NC], cap2[NC], capx[NC];
+            for (int k = 0; k < NC; ++k) flux[k] = ringA[k] = ringB[k] = across[k] = cap1[k] = cap2[k] = capx[k] = C(0);
+            static_for<0, Lat<D>::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+                constexpr int off = (cz * T::LY + cy) * T::LX + cx;
+                constexpr C w3 = C(3.0 * weight<D>(i));
+                const C p1 = fabs(s_psi[lc0 + off]), p2 = fabs(s_psi[lc0 + 2 * off]), m1 = fabs(s_psi[lc0 - off]);
+                const C r1 = s_rho[lc0 + off], r2 = s_rho[lc0 + 2 * off], rm = s_rho[lc0 - off];
+                static_for<0, NC>([&](auto K) {
+                    constexpr int k = decltype(K)::value;
+                    constexpr int cc = Lat<D>::c(i, ca[k]) * Lat<D>::c(i, cb[k]);
+                    if constexpr (cc != 0) {
+                        flux[k] += C(cc) * h[i];
+                        constexpr C wc = w3 * C(cc);
+                        ringA[k] += wc * p1;
+                        ringB[k] += wc * p2;
+                        across[k] += wc * m1 * p1;
+                        cap1[k] += wc * r1;
+                        cap2[k] += wc * r2;
+                        capx[k] += wc * rm * r1;
+                    }
+                });
+            });
+            const C rho = s_rho[lc0], sp = s_psi[lc0];
+            const C psi = fabs(sp), sg = sp > C(0) ? C(1) : C(-1);
+            for (int k = 0; k < NC; ++k) {
+                const C PA = -sg * C(8.0 / 6.0) * psi * ringA[k];
+                const C PB = sg * C(1.0 / 6.0) * (psi * ringB[k] + across[k]);
+                const C PC = -p.kappa * rho * cap1[k];
+                const C PD = C(0.5) * p.kappa * (rho * cap2[k] + capx[k]);
+                // FP32 deviation storage: the reference part w_i rho_ref adds rho_ref/3 on the diagonal
+                const C kin = flux[k] + (k < D ? p.rho_ref * C(1.0 / 3.0) : C(0));
+                out_U[(long long)k * g.N + n] = double(kin) - (double(PA) + double(PB) + double(PC) + double(PD));
             }
             continue;
         }
@@ -352,6 +403,12 @@ template <int D, class S, class C, bool MASK> struct Launch {
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_STEP>), collide_grid(g), dim3(256), 0, s, (const S *)A, (S *)B, g,
                            mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, nullptr, nullptr);
     }
+    static void pressure(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm,
+                         const void *rho, double *out) {
+        hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_PT>), collide_grid(g), dim3(256), 0, s, (const S *)A,
+                           (S *)nullptr, g, mask, *(const Params<C> *)prm, (const C *)rho, (const C *)nullptr, nullptr,
+                           out);
+    }
     static void output(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm,
                        const void *rho, const void *gfl, double *orho, double *oU) {
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_OUT>), collide_grid(g), dim3(256), 0, s, (const S *)A,
@@ -364,6 +421,7 @@ template <int D, class S, class C, bool MASK> struct Launch {
         k.moments = moments;
         k.collide = collide;
         k.output = output;
+        k.pressure = pressure;
         k.moment_blocks = 0;
         return k;
     }

@@ -25,7 +25,7 @@ EXPORTED = [
     "lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments", "lbm_destroy", "lbm_last_error",
     "lbm_set_stream", "lbm_population_bytes", "lbm_get_populations", "lbm_set_populations",
     "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_surface_tension",
-    "lbm_eos_pressure", "lbm_batch_create",
+    "lbm_eos_pressure", "lbm_pressure_tensor", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
     "lbm_batch_last_error",
 ]
@@ -79,6 +79,7 @@ def lib() -> C.CDLL:
         L.lbm_kappa_for_width.argtypes = [P, d, C.POINTER(d)]
         L.lbm_surface_tension.argtypes = [P, C.POINTER(d)]
         L.lbm_eos_pressure.argtypes = [P, vp, i64, vp]
+        L.lbm_pressure_tensor.argtypes = [vp, vp]
         L.lbm_batch_create.argtypes = [P, C.c_int, C.POINTER(vp)]
         L.lbm_batch_init_fields.argtypes = [vp, C.c_int, vp, vp]
         L.lbm_batch_step.argtypes = [vp, i64]
@@ -252,6 +253,14 @@ def lbm_eos_pressure(p: Params, rho) -> np.ndarray:
     out = np.empty_like(r)
     _check(lib().lbm_eos_pressure(C.byref(cp), _ptr(r), r.size, _ptr(out)), None)
     return out
+
+
+def lbm_pressure_tensor(ctx, N: int, lattice: int) -> np.ndarray:
+    """[D(D+1)/2, N] discrete pressure tensor: xx, yy, xy (D2Q9) or xx, yy, zz, xy, xz, yz."""
+    nc = 6 if lattice == LBM_D3Q27 else 3
+    out = np.empty(nc * N)
+    _check(lib().lbm_pressure_tensor(ctx, _ptr(out)), ctx)
+    return out.reshape(nc, N)
 
 
 def lbm_batch_create(cases: list[Params]):

@@ -15,6 +15,8 @@ rho_v to 0 at rho_w = rho_l. The paper maps it with a liquid column in a channel
   the 2D Young-Laplace law P_in - P_out = -2 sigma cos(theta) / H.
 - calibrate / wall_density_for_angle: the angle as a function of rho_w over a list of
   densities, and its inverse by interpolation in cos(theta).
+- kirkwood_buff_integral: the surface tension of flat interfaces from the discrete
+  pressure tensor (lbm_pressure_tensor), a second measure beside Laplace's law.
 
 The paper prints the Young-Laplace law with sin(theta); that form vanishes at both ends
 of the angle range it reports, so the cosine law is used here.
@@ -139,6 +141,20 @@ def calibrate(base: P.Params, rho_walls, H: int = 40, **kw) -> list[dict]:
     if sigma is None:
         sigma = effective_surface_tension(base, width=kw.get("width", 4.0))
     return [column_angle(base, float(r), H, sigma=sigma, **kw) for r in rho_walls]
+
+
+def kirkwood_buff_integral(tensor: np.ndarray, lattice: int, nx: int, ny: int, nz: int = 1, axis: int = 0) -> float:
+    """Integral of P_nn - P_tt along the normal `axis` of flat interfaces (Kirkwood-Buff,
+    Sec. 3.2), from lbm_pressure_tensor's output, averaged over the transverse nodes and
+    tangential directions: the surface tension summed over the interfaces crossed."""
+    D = 3 if lattice == P.LBM_D3Q27 else 2
+    shape = (nz, ny, nx) if D == 3 else (ny, nx)
+    diag = [tensor[a].reshape(shape) for a in range(D)]
+    ax = D - 1 - axis                                        # array axis of the normal direction
+    tang = [diag[a] for a in range(D) if a != axis]
+    diff = diag[axis] - sum(tang) / len(tang)
+    other = tuple(k for k in range(D) if k != ax)
+    return float(diff.mean(axis=other).sum())
 
 
 def wall_density_for_angle(table: list[dict], theta: float, key: str = "theta_geom") -> float:
