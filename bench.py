@@ -243,6 +243,29 @@ def tapered_posts_workload(P, torch, a3, d0=64):
     return res
 
 
+def pressure_tensor_leg(P, torch, n, reps=3):
+    """The discrete pressure tensor (Appendix E) of the drop workload after 20 steps, FP32 and
+    FP64: wall time per lbm_pressure_tensor call (moment pass, tensor kernel, and the copy of
+    6 FP64 components per node to the host)."""
+    out = {}
+    for prec, name in ((P.LBM_FP32_DEV, "fp32"), (P.LBM_FP64, "fp64")):
+        p, rho0, _ = workload(P, n, prec)
+        with P.Simulation(p) as s:
+            s.init(rho0)
+            s.step(20)
+            P.lbm_pressure_tensor(s.ctx, n ** 3, P.LBM_D3Q27)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Pt = P.lbm_pressure_tensor(s.ctx, n ** 3, P.LBM_D3Q27)
+            dt = (time.perf_counter() - t0) / reps
+            c = n // 2
+            centre = Pt[:, c + n * (c + n * c)]
+        out[name] = {"call_s": dt, "centre_xx_yy_zz": [float(v) for v in centre[:3]],
+                     "finite": bool(np.isfinite(Pt).all())}
+    return out
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on a bounded sample of the same workload (48^3, same physics)."""
     from oracle import oracle as O
@@ -279,6 +302,8 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2, drop-impact and posts legs")
     ap.add_argument("--posts-only", action="store_true",
                     help="run only the tapered-posts leg (curved walls) and print its JSON line")
+    ap.add_argument("--pressure-only", action="store_true",
+                    help="time only the discrete pressure tensor of the 256^3 drop and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -290,6 +315,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.pressure_only:
+        print(json.dumps({"pressure_tensor_256": pressure_tensor_leg(P, torch, args.size)}), flush=True)
+        return
     if args.posts_only:
         base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
         a3 = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)
