@@ -37,8 +37,13 @@ def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
 
 def uniform_pm(seed: int, count: int, amplitude: float) -> np.ndarray:
     """Uniform numbers in [-amplitude, amplitude) from 53-bit SplitMix64 mantissas."""
-    u = (splitmix64(seed, count) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
-    return amplitude * (2.0 * u - 1.0)
+    out = np.empty(count, dtype=np.float64)
+    block = 1 << 22                       # bounded temporaries for lattices of 10^8+ nodes
+    for s in range(0, count, block):
+        k = min(block, count - s)
+        u = (splitmix64(seed, k, s) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+        out[s:s + k] = amplitude * (2.0 * u - 1.0)
+    return out
 
 
 def _grid(nx: int, ny: int, nz: int):
@@ -61,7 +66,10 @@ def add_noise(rho: np.ndarray, seed: int, amplitude: float) -> np.ndarray:
     """Multiplicative noise rho * (1 + eta), eta ~ U(-amplitude, amplitude) per node."""
     if amplitude == 0.0:
         return rho.copy()
-    return rho * (1.0 + uniform_pm(seed, rho.size, amplitude))
+    eta = uniform_pm(seed, rho.size, amplitude)
+    eta += 1.0
+    eta *= rho
+    return eta
 
 
 def flat_slab(nx: int, ny: int, nz: int, rho_liquid: float, rho_vapour: float, width: float,
@@ -81,11 +89,14 @@ def flat_slab(nx: int, ny: int, nz: int, rho_liquid: float, rho_vapour: float, w
 def drop(nx: int, ny: int, nz: int, radius: float, rho_liquid: float, rho_vapour: float,
          width: float, centre=None, noise: float = 0.0, seed: int = 0, bubble: bool = False) -> np.ndarray:
     """Circular (nz == 1) or spherical drop of the liquid in vapour (or a bubble if `bubble`)."""
-    x, y, z = _grid(nx, ny, nz)
     if centre is None:
         centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
     cx, cy, cz = centre
-    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + ((z - cz) ** 2 if nz > 1 else 0.0))
+    # squared offsets per axis, broadcast over the lattice (no full-size coordinate arrays)
+    dx2 = (np.arange(nx, dtype=np.float64) - cx) ** 2
+    dy2 = (np.arange(ny, dtype=np.float64) - cy) ** 2
+    dz2 = (np.arange(nz, dtype=np.float64) - cz) ** 2 if nz > 1 else np.zeros(nz)
+    r = np.sqrt((dx2[None, None, :] + dy2[None, :, None]) + dz2[:, None, None]).ravel()
     d = radius - r
     if bubble:
         d = -d

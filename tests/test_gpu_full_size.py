@@ -49,6 +49,41 @@ def test_bench_workload_256cubed_sampled_nodes(precision):
     assert np.isfinite(tot).all()
 
 
+# ------------------------------------------------------------------ 600^3: populations past 4 GiB
+SAMPLES600 = [(300, 300, 300), (400, 300, 300), (300, 230, 370), (63, 7, 300), (64, 8, 301), (575, 300, 300),
+              (576, 301, 299), (599, 599, 599), (0, 0, 0), (599, 0, 300), (300, 599, 0)]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_drop_600cubed_grouped_resources_sampled_nodes(precision):
+    # 600^3 nodes (the largest lattice of Sec. 5): one population of the FP32 lattice is 0.86 GB and
+    # the 27 exceed the 4 GiB one buffer resource reaches, FP64 even 14 of them, so the fused step
+    # addresses the lattice through one resource per group of populations; 600 = 9 x 64 + 24 also
+    # leaves a ragged column of x tiles, and the rows are padded to 608.
+    import paper_2112_01975_amd as P
+    case = Case(3, 600, 600, 600, eos=T.PR, a=A_PR06, acentric=0.344, T_reduced=0.6, kappa=0.02, tau=0.8)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(600, 600, 600, 100.0, rl, rv, 5.0, noise=1e-5, seed=1007)
+    rho_ref = rv if precision == 1 else 0.0
+    with P.Simulation(case.params(precision, rho_ref, check_every=-1)) as s:
+        s.init(rho0).step(30)
+        _, nl = P.lbm_step_timed(s.ctx, 10)
+        assert nl[0] == 0, "the step did not take the fused kernel"
+        pops = P.lbm_get_populations(s.ctx)
+        s.step(1)
+        r, U, tot = s.moments()
+    del rho0
+    ref = oracle_one_step_at_nodes(case, pops, precision, rho_ref, SAMPLES600)
+    del pops
+    r3 = r.reshape(600, 600, 600)
+    U3 = U.reshape(3, 600, 600, 600)
+    rtol, utol = (1e-12, 1e-13) if precision == 0 else (2e-6, 2e-7)
+    for (x, y, z), (ro, Uo) in zip(SAMPLES600, ref):
+        assert abs(r3[z, y, x] / ro - 1) < rtol, ((x, y, z), r3[z, y, x], ro)
+        assert np.abs(U3[:, z, y, x] - Uo).max() < utol, ((x, y, z), U3[:, z, y, x], Uo)
+    assert np.isfinite(tot).all()
+
+
 # ------------------------------------------------------------------ drop impact on a textured wall
 IMPACT_SAMPLES = [(4, 4, 17), (8, 4, 10), (12, 12, 1), (256, 128, 77), (256, 128, 37), (100, 50, 255),
                   (511, 255, 16), (7, 7, 16)]
