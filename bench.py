@@ -38,17 +38,40 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def workload(P, n, precision, check_every=-1):
-    """Params and initial density of the static-drop workload at n^3."""
-    base = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
+def workload(P, n, precision, check_every=-1, box=None):
+    """Params and initial density of the static-drop workload at n^3 (or at box = (nx, ny,
+    nz), the drop radius scaled with the smallest side)."""
+    nx, ny, nz = box or (n, n, n)
+    base = P.Params(P.LBM_D3Q27, nx, ny, nz, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
     a = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)   # kappa(W) is linear in a at fixed b, T/Tc
-    p = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_PR, a, B21, 1.0, 0.344, 0.6, 0.02, 0.8,
+    p = P.Params(P.LBM_D3Q27, nx, ny, nz, P.LBM_EOS_PR, a, B21, 1.0, 0.344, 0.6, 0.02, 0.8,
                  precision=precision, check_every=check_every)
     rv, rl, _, _ = P.lbm_coexistence(p)
     p.rho_ref = rv if precision == P.LBM_FP32_DEV else 0.0
     import lbm_inputs as L
-    rho0 = L.drop(n, n, n, 50.0 * n / 256.0, rl, rv, 5.0, noise=1e-5, seed=1003)
+    rho0 = L.drop(nx, ny, nz, 50.0 * min(nx, ny, nz) / 256.0, rl, rv, 5.0, noise=1e-5, seed=1003)
     return p, rho0, (rv, rl, a)
+
+
+def size_sweep(P, torch, boxes, steps=10, warmup=3):
+    """The FP32 drop's fused step at other lattice sizes: ms per step from HIP events
+    (lbm_step_timed) and GLUPS; ends with the copy probe so that counter runs of this leg
+    carry their own scale."""
+    out = {}
+    for box in boxes:
+        p, rho0, _ = workload(P, 0, P.LBM_FP32_DEV, box=box)
+        with P.Simulation(p) as sim:
+            sim.init(rho0)
+            del rho0
+            P.lbm_step(sim.ctx, warmup)
+            ms, nl = P.lbm_step_timed(sim.ctx, steps)
+            _, _, tot = sim.moments(want_fields=False)
+        name = "x".join(str(v) for v in box)
+        out[name] = {"ms_per_step": round(ms[1] / steps, 4), "GLUPS": round(p.N * steps / ms[1] / 1e6, 2),
+                     "fused": bool(nl[0] == 0), "finite": bool(np.isfinite(tot).all())}
+        log(f"[bench] size {name}: {out[name]}")
+    out["copy_probe_GBs"] = round(copy_probe(torch)["GBs"], 1)
+    return out
 
 
 def time_leg(P, torch, n, precision, steps, warmup):
@@ -304,6 +327,8 @@ def main():
                     help="run only the tapered-posts leg (curved walls) and print its JSON line")
     ap.add_argument("--pressure-only", action="store_true",
                     help="time only the discrete pressure tensor of the 256^3 drop and print its JSON line")
+    ap.add_argument("--sizes-only", default=None, metavar="NXxNYxNZ,...",
+                    help="time only the FP32 drop's fused step at these lattice sizes and print their JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: the step runs on one GPU, --gpus must be 1",
@@ -315,6 +340,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.sizes_only:
+        boxes = [tuple(int(v) for v in b.split("x")) for b in args.sizes_only.split(",")]
+        print(json.dumps({"fp32_drop_sizes": size_sweep(P, torch, boxes)}), flush=True)
+        return
     if args.pressure_only:
         print(json.dumps({"pressure_tensor_256": pressure_tensor_leg(P, torch, args.size)}), flush=True)
         return
