@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2, drop-impact and posts legs")
     ap.add_argument("--posts-only", action="store_true",
                     help="run only the tapered-posts leg (curved walls) and print its JSON line")
+    ap.add_argument("--posts-d0", type=int, default=64,
+                    help="post spacing scale D0 of the posts leg; the box is 4 D0 (150: the paper's 600^3)")
     ap.add_argument("--pressure-only", action="store_true",
                     help="time only the discrete pressure tensor of the 256^3 drop and print its JSON line")
     ap.add_argument("--sizes-only", default=None, metavar="NXxNYxNZ,...",
@@ -350,7 +352,8 @@ def main():
     if args.posts_only:
         base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
         a3 = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)
-        print(json.dumps({"d3q27_256_tapered_posts": tapered_posts_workload(P, torch, a3)}), flush=True)
+        d0 = args.posts_d0
+        print(json.dumps({f"d3q27_{4 * d0}_tapered_posts": tapered_posts_workload(P, torch, a3, d0)}), flush=True)
         return
     n = args.size
     N = n ** 3

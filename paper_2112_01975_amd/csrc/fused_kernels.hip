@@ -553,9 +553,16 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         __syncthreads();
         shift_windows(gzn, buf);
     };
+    // FP32: planes whose pulls cannot bounce back take the unmasked body (a uniform branch).
+    // FP64 keeps one body: the two bodies in one loop cost it hundreds of spilled registers,
+    // more than the per-link selects cost on the few solid-free planes of a masked run.
     auto march = [&](int k, C (&qa)[27], C (&ma)[4]) __attribute__((always_inline)) {
-        if (plane_flags(z0 + k + 3) & 2u) march_body(k, qa, ma, std::integral_constant<bool, MASK>{});
-        else march_body(k, qa, ma, std::false_type{});
+        if constexpr (REPULL) {
+            march_body(k, qa, ma, std::integral_constant<bool, MASK>{});
+        } else {
+            if (plane_flags(z0 + k + 3) & 2u) march_body(k, qa, ma, std::integral_constant<bool, MASK>{});
+            else march_body(k, qa, ma, std::false_type{});
+        }
     };
 
     prologue_plane(-2, q0, m0);
