@@ -98,3 +98,20 @@ def test_batch_rejects_interpolated_walls_without_gpu():
     with pytest.raises(P.LbmError) as ei:
         P.lbm_batch_create([p])
     assert ei.value.code == P.LBM_E_INVAL and "not supported by the batch" in str(ei.value)
+
+
+def test_velocity_sets_are_the_full_stencils():
+    # D2Q9 / D3Q27 are the tensor products of {-1, 0, 1} per axis (Sec. 2.3, the D3Q27 set and its
+    # 2D reduction without the z component); the rest
+    # velocity comes first, D2Q9 has no z component, and every velocity has its opposite
+    import itertools
+    import paper_2112_01975_amd as P
+    for lattice, D, Q in ((P.LBM_D2Q9, 2, 9), (P.LBM_D3Q27, 3, 27)):
+        c = np.asarray(P.lbm_velocities(lattice))
+        assert c.shape == (Q, 3)
+        assert (c[0] == 0).all()
+        assert set(map(tuple, c[:, :D].tolist())) == set(itertools.product((-1, 0, 1), repeat=D))
+        if D == 2:
+            assert (c[:, 2] == 0).all()
+        rows = set(map(tuple, c.tolist()))
+        assert all(tuple(-v for v in r) in rows for r in rows)
