@@ -101,9 +101,9 @@ def test_batch_rejects_interpolated_walls_without_gpu():
 
 
 def test_velocity_sets_are_the_full_stencils():
-    # D2Q9 / D3Q27 are the tensor products of {-1, 0, 1} per axis (Sec. 2.3, the D3Q27 set and its
-    # 2D reduction without the z component); the rest
-    # velocity comes first, D2Q9 has no z component, and every velocity has its opposite
+    # D2Q9 / D3Q27 are the tensor products of {-1, 0, 1} per axis (Sec. 2.3: the D3Q27 set, and
+    # D2Q9 as its reduction without the z component); the rest velocity comes first and every
+    # velocity has its opposite
     import itertools
     import paper_2112_01975_amd as P
     for lattice, D, Q in ((P.LBM_D2Q9, 2, 9), (P.LBM_D3Q27, 3, 27)):
