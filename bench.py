@@ -309,7 +309,26 @@ def cpu_baseline(budget_s=12.0):
     dt = time.perf_counter() - t0
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": O.max_threads(), "kind": "oracle",
             "sample": f"D3Q27 {n}^3 drop (same EOS, T/Tc, kappa, tau; radius scaled to 9.4), {steps} FP64 "
-                      f"steps in {dt:.1f} s"}
+                      f"steps in {dt:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, and those this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity}
 
 
 def main():
