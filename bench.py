@@ -53,6 +53,19 @@ def workload(P, n, precision, check_every=-1, box=None):
     return p, rho0, (rv, rl, a)
 
 
+def density_error(rho32, rho64, n):
+    """FP32 against FP64 density of the n^3 drop: largest pointwise relative difference, and
+    the relative differences of the mean densities of a 4^3 block at the liquid centre and
+    at the vapour corner."""
+    c = n // 2
+    a, b = rho32.reshape(n, n, n), rho64.reshape(n, n, n)
+    centre = (slice(c - 2, c + 2),) * 3
+    corner = (slice(0, 4),) * 3
+    return {"max_pointwise_rel": float(np.max(np.abs(rho32 - rho64) / rho64)),
+            "liquid_centre_rel": float(abs(a[centre].mean() / b[centre].mean() - 1)),
+            "vapour_corner_rel": float(abs(a[corner].mean() / b[corner].mean() - 1))}
+
+
 def size_sweep(P, torch, boxes, steps=10, warmup=3):
     """The FP32 drop's fused step at other lattice sizes: ms per step from HIP events
     (lbm_step_timed) and GLUPS; ends with the copy probe so that counter runs of this leg
@@ -389,13 +402,21 @@ def main():
         sim64, r64, _ = time_leg(P, torch, n, P.LBM_FP64, args.steps, args.warmup)
         log(f"[bench] FP64 {r64['mlups']:.0f} MLUPS, kernels {r64['kernel_ms']}")
         rho64, _, t64 = sim64.moments()
-        c = n // 2
-        r3a, r3b = rho32.reshape(n, n, n), rho64.reshape(n, n, n)
-        dens = {"after_steps": r32["steps_total"],
-                "max_pointwise_rel": float(np.max(np.abs(rho32 - rho64) / rho64)),
-                "liquid_centre_rel": float(abs(r3a[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
-                                               / r3b[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean() - 1)),
-                "vapour_corner_rel": float(abs(r3a[:4, :4, :4].mean() / r3b[:4, :4, :4].mean() - 1))}
+        dens = {"after_steps": r32["steps_total"], "rho_ref": "rho_vapour", **density_error(rho32, rho64, n)}
+        # the other references the deviation storage could take (liquid density, mean of the two)
+        alt = {}
+        for name, ref in (("rho_liquid", rl), ("mean", 0.5 * (rl + rv))):
+            p_alt, rho0_alt, _ = workload(P, n, P.LBM_FP32_DEV)
+            p_alt.rho_ref = ref
+            with P.Simulation(p_alt) as s_alt:
+                s_alt.init(rho0_alt)
+                del rho0_alt
+                s_alt.step(r32["steps_total"])
+                rho_alt, _, _ = s_alt.moments()
+            alt[name] = density_error(rho_alt, rho64, n)
+            del rho_alt
+        dens["other_rho_ref"] = alt
+        log(f"[bench] FP32 density error {dens}")
         t_k = r64["kernel_ms"]["step_kernel"] * 1e-3
         b64 = (2 * 27 + 4) * 8 if not r64["fused"] else 2 * 27 * 8
         fp64 = {"value": r64["mlups"], "unit": "MLUPS", "ms_per_step": r64["ms_per_step"],
