@@ -322,6 +322,7 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
         free_batch(b);
         return bfail(nullptr, LBM_E_HIP, "descriptor upload failed");
     }
+    // LBM2P_BATCH_CHUNK: steps per captured graph launch (default 200)
     const char *cs = getenv("LBM2P_BATCH_CHUNK");
     b->chunk = (cs && atoi(cs) > 0) ? atoi(cs) : 200;
     *out = b;
@@ -357,8 +358,10 @@ static int autotune(lbm_batch *b) {
         auto it = g_tune_cache.find(sig);
         if (it != g_tune_cache.end()) { b->block = it->second; return LBM_OK; }
     }
+    // LBM2P_BATCH_BLOCK: a fixed workgroup size, a multiple of 64 up to 1024 (others are ignored)
     const char *env = getenv("LBM2P_BATCH_BLOCK");
-    if (env && atoi(env) > 0) { b->block = atoi(env); return LBM_OK; }
+    const int fixed = env ? atoi(env) : 0;
+    if (fixed >= 64 && fixed <= 1024 && fixed % 64 == 0) { b->block = fixed; return LBM_OK; }
     // timed trials of a few steps on the live state, then the state is rewound: the trials
     // run an even number of steps on copies taken and restored through the graph-free path
     int best = 256;
