@@ -77,13 +77,15 @@ def test_flat_interface_uniform_normal_pressure_and_kirkwood_buff_tension():
     assert abs(sigma_kb / sigma_lap - 1) < 0.02
 
 
-def test_surface_of_tension_and_tolman_length_of_drops_from_the_gpu_tensor():
-    # Sec. 3.4 on drops at rest (D2Q9, vdW T/Tc = 0.7, W = 4, R = 24 and 36 in 128^2): sigma(R) from
-    # the tangential pressure of the GPU tensor, fitted by the curvature law. The tensor's bulk
-    # pressures are the EOS pressures of the bulk densities; Laplace's law with the equimolar
-    # radius gives the flat interface's Kirkwood-Buff tension; the surface of tension lies inside
-    # the equimolar surface by a Tolman length shorter than the interface width, the same for
-    # both drops, and the Tolman fit of the two (sigma_s, R_s) returns it.
+def test_surface_of_tension_and_tolman_length_of_drops_and_bubbles_from_the_gpu_tensor():
+    # Sec. 3.4 on drops and bubbles at rest (D2Q9, vdW T/Tc = 0.7, W = 4, R = 24 and 36 in 128^2):
+    # sigma(R) from the tangential pressure of the GPU tensor, fitted by the curvature law.
+    # - the tensor's bulk pressures are the EOS pressures of the bulk densities;
+    # - Laplace's law with the equimolar radius gives the flat interface's Kirkwood-Buff tension;
+    # - the surface of tension lies inside the equimolar surface of a drop and outside that of a
+    #   bubble, by a Tolman length shorter than the interface width and the same for both sizes;
+    # - the Tolman fit (minus sign for drops, plus for bubbles) returns that length, and drops and
+    #   bubbles give lengths of the same size (the paper finds them equal).
     import paper_2112_01975_amd as P
     from paper_2112_01975_amd import capillarity as Cp
     from paper_2112_01975_amd import wetting as Wt
@@ -98,32 +100,35 @@ def test_surface_of_tension_and_tolman_length_of_drops_from_the_gpu_tensor():
         sigma_flat = Wt.kirkwood_buff_integral(P.lbm_pressure_tensor(s.ctx, 64 * 4, P.LBM_D2Q9), P.LBM_D2Q9, 64, 4) / 2
     n = 128
     p = P.Params(P.LBM_D2Q9, n, n, 1, P.LBM_EOS_VDW, a, 2 / 21, 1.0, 0.0, 0.7, 0.02, 0.8)
-    res = []
-    for R0 in (24.0, 36.0):
-        with P.Simulation(p) as s:
-            s.init(L.drop(n, n, 1, R0, rl, rv, W))
-            s.step(20000)
-            rho, _, _ = s.moments()
-            Pt = P.lbm_pressure_tensor(s.ctx, n * n, P.LBM_D2Q9)
-        r, _ = Cp.tangential_pressure(Pt, P.LBM_D2Q9, n, n)
-        trace = (Pt[0] + Pt[1]) / 2
-        p_in, p_out = float(trace[r < 8].mean()), float(trace[r > 58].mean())
-        r_in, r_out = float(rho[r < 8].mean()), float(rho[r > 58].mean())
-        eos_in, eos_out = P.lbm_eos_pressure(p, np.array([r_in, r_out]))
-        # (the EOS of the mean bulk density against the mean bulk tensor)
-        assert abs(p_in - eos_in) < 1e-4 * p_in and abs(p_out - eos_out) < 1e-4 * p_in
-        radii = np.linspace(5.0, 60.0, 17)
-        sig = Cp.notional_surface_tension(Pt, P.LBM_D2Q9, n, n, 1, radii, p_in, p_out)
-        ss, rs = Cp.fit_surface_of_tension(radii, sig, 2)
-        re = Cp.equimolar_radius(rho, 2, r_in, r_out)
-        res.append((ss, rs, re, p_in - p_out))
-        print(f"R0 {R0}: sigma_s {ss:.5f} R_s {rs:.3f} R_e {re:.3f} dP*R_e {(p_in - p_out) * re:.5f} "
-              f"flat {sigma_flat:.5f}", flush=True)
-    for ss, rs, re, dp in res:
-        assert abs(dp * re / sigma_flat - 1) < 0.02
-        assert 0 < re - rs < W
-    d1, d2 = (re - rs for _, rs, re, _ in res)
-    assert abs(d1 / d2 - 1) < 0.15, (d1, d2)
-    dt = Cp.tolman_length([rs for _, rs, _, _ in res], [ss for ss, _, _, _ in res], sigma_flat, 2)
-    print(f"Tolman length {dt:.3f}, R_e - R_s {d1:.3f} {d2:.3f}", flush=True)
-    assert abs(dt / (0.5 * (d1 + d2)) - 1) < 0.1
+    tolman = {}
+    for bubble in (False, True):
+        res = []
+        for R0 in (24.0, 36.0):
+            with P.Simulation(p) as s:
+                s.init(L.drop(n, n, 1, R0, rl, rv, W, bubble=bubble))
+                s.step(20000)
+                rho, _, _ = s.moments()
+                Pt = P.lbm_pressure_tensor(s.ctx, n * n, P.LBM_D2Q9)
+            r, _ = Cp.tangential_pressure(Pt, P.LBM_D2Q9, n, n)
+            trace = (Pt[0] + Pt[1]) / 2
+            p_in, p_out = float(trace[r < 8].mean()), float(trace[r > 58].mean())
+            r_in, r_out = float(rho[r < 8].mean()), float(rho[r > 58].mean())
+            eos_in, eos_out = P.lbm_eos_pressure(p, np.array([r_in, r_out]))
+            # (the EOS of the mean bulk density against the mean bulk tensor)
+            scale = max(p_in, p_out)
+            assert abs(p_in - eos_in) < 1e-4 * scale and abs(p_out - eos_out) < 1e-4 * scale
+            radii = np.linspace(5.0, 60.0, 17)
+            sig = Cp.notional_surface_tension(Pt, P.LBM_D2Q9, n, n, 1, radii, p_in, p_out)
+            ss, rs = Cp.fit_surface_of_tension(radii, sig, 2)
+            re = Cp.equimolar_radius(rho, 2, r_in, r_out)
+            res.append((ss, rs, re))
+            print(f"{'bubble' if bubble else 'drop'} R0 {R0}: sigma_s {ss:.5f} R_s {rs:.3f} R_e {re:.3f} "
+                  f"dP*R_e {(p_in - p_out) * re:.5f} flat {sigma_flat:.5f}", flush=True)
+            assert abs((p_in - p_out) * re / sigma_flat - 1) < 0.02
+        d = [(rs - re) if bubble else (re - rs) for _, rs, re in res]
+        assert all(0 < v < W for v in d), d
+        assert abs(d[0] / d[1] - 1) < 0.15, d
+        dt = Cp.tolman_length([rs for _, rs, _ in res], [ss for ss, _, _ in res], sigma_flat, 2, bubble=bubble)
+        assert abs(dt / np.mean(d) - 1) < 0.1, (dt, d)
+        tolman[bubble] = dt
+    assert abs(tolman[True] / tolman[False] - 1) < 0.3, tolman
