@@ -132,3 +132,53 @@ def test_surface_of_tension_and_tolman_length_of_drops_and_bubbles_from_the_gpu_
         assert abs(dt / np.mean(d) - 1) < 0.1, (dt, d)
         tolman[bubble] = dt
     assert abs(tolman[True] / tolman[False] - 1) < 0.3, tolman
+
+
+def test_surface_of_tension_of_d3q27_drops_from_the_gpu_tensor():
+    # The 3D analysis (tangential pressure averaged over the two directions normal to the radius,
+    # sphere area 4 pi) on drops stepped by the fused D3Q27 kernel: vdW T/Tc = 0.7, W = 4,
+    # R = 24 and 36 in 128^3, FP64, 30000 steps. The flat tension from a 3D slab; the bulk tensor
+    # is the EOS pressure; Laplace with the equimolar radius, Delta P R_e / 2, gives the flat
+    # tension; the surface of tension lies inside the equimolar sphere by less than W, by the same
+    # distance for both sizes, and the leading-order Tolman fit gives the same length for both.
+    import paper_2112_01975_amd as P
+    from paper_2112_01975_amd import capillarity as Cp
+    from paper_2112_01975_amd import wetting as Wt
+    W = 4.0
+    base = P.Params(P.LBM_D3Q27, 8, 4, 4, P.LBM_EOS_VDW, 9 / 49, 2 / 21, 1.0, 0.0, 0.7, 0.02, 0.8)
+    a = 9 / 49 * 0.02 / P.lbm_kappa_for_width(base, W)
+    slab = P.Params(P.LBM_D3Q27, 64, 4, 4, P.LBM_EOS_VDW, a, 2 / 21, 1.0, 0.0, 0.7, 0.02, 0.8)
+    rv, rl, _, _ = P.lbm_coexistence(slab)
+    with P.Simulation(slab) as s:
+        s.init(L.flat_slab(64, 4, 4, rl, rv, W))
+        s.step(40000)
+        sigma_flat = Wt.kirkwood_buff_integral(P.lbm_pressure_tensor(s.ctx, 64 * 16, P.LBM_D3Q27),
+                                               P.LBM_D3Q27, 64, 4, 4) / 2
+    n = 128
+    p = P.Params(P.LBM_D3Q27, n, n, n, P.LBM_EOS_VDW, a, 2 / 21, 1.0, 0.0, 0.7, 0.02, 0.8)
+    res = []
+    for R0 in (24.0, 36.0):
+        with P.Simulation(p) as s:
+            s.init(L.drop(n, n, n, R0, rl, rv, W))
+            s.step(30000)
+            rho, _, _ = s.moments()
+            Pt = P.lbm_pressure_tensor(s.ctx, n ** 3, P.LBM_D3Q27)
+        r, _ = Cp.tangential_pressure(Pt, P.LBM_D3Q27, n, n, n)
+        trace = (Pt[0] + Pt[1] + Pt[2]) / 3
+        p_in, p_out = float(trace[r < 10].mean()), float(trace[r > 58].mean())
+        r_in, r_out = float(rho[r < 10].mean()), float(rho[r > 58].mean())
+        eos_in, eos_out = P.lbm_eos_pressure(p, np.array([r_in, r_out]))
+        assert abs(p_in - eos_in) < 1e-3 * p_in and abs(p_out - eos_out) < 1e-3 * p_in
+        radii = np.linspace(5.0, 60.0, 17)
+        sig = Cp.notional_surface_tension(Pt, P.LBM_D3Q27, n, n, n, radii, p_in, p_out)
+        ss, rs = Cp.fit_surface_of_tension(radii, sig, 3)
+        re = Cp.equimolar_radius(rho, 3, r_in, r_out)
+        print(f"3D drop R0 {R0}: sigma_s {ss:.5f} R_s {rs:.3f} R_e {re:.3f} "
+              f"dP*R_e/2 {(p_in - p_out) * re / 2:.5f} flat {sigma_flat:.5f}", flush=True)
+        assert abs((p_in - p_out) * re / 2 / sigma_flat - 1) < 0.02
+        assert 0 < re - rs < W
+        res.append((ss, rs, re))
+    d = [re - rs for _, rs, re in res]
+    assert abs(d[0] / d[1] - 1) < 0.15, d
+    t = [(1 - ss / sigma_flat) * rs / 2 for ss, rs, _ in res]     # sigma_s = sigma_0 (1 - 2 delta / R_s)
+    assert abs(t[0] / t[1] - 1) < 0.15, t
