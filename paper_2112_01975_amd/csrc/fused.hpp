@@ -1,5 +1,7 @@
 // fused.hpp -- launch interface of the single-pass D3Q27 step (z-march).
 #pragma once
+
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,11 +14,18 @@ struct FusedGrid {
     int zb, ze;            // the launch collides planes [zb, ze), in chunks of tz from zb
     int ntx, nty, nzc;     // tiles in x, y and z-chunks
     int items;             // ntx * nty * nzc work items
-    int per_xcd;           // items per XCD (ceil(items / 8))
+    int item0, count;      // this launch runs items [item0, item0 + count)
+    int per_xcd;           // items per XCD (ceil(count / 8))
     int blocks;            // launched workgroups = 8 * per_xcd
 };
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze);
+
+// The launches of one grid: windows of at most `window` consecutive items, so that each
+// round of work items starts together (neighbouring tiles then march in step and share
+// their halo lines in L2, which later rounds of one launch, started as earlier items
+// finish, do not).
+std::vector<FusedGrid> fused_windows(const FusedGrid &fg, int window);
 
 // Solid geometry for the fused step (nullptr without solid nodes):
 //   links[n]  per-node solid-neighbour bits from fused_links;

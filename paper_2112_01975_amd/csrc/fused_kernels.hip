@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fused.hpp"
@@ -263,8 +264,9 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
 
     // XCD-aware work item: consecutive items on one XCD are spatial neighbours
     const int b = blockIdx.x;
-    const int item = (b % NXCD) * fg.per_xcd + b / NXCD;
-    if (item >= fg.items) return;
+    const int local = (b % NXCD) * fg.per_xcd + b / NXCD;
+    if (local >= fg.count) return;
+    const int item = fg.item0 + local;
     const int tix = item % fg.ntx;
     const int rest = item / fg.ntx;
     const int tiy = rest % fg.nty;
@@ -657,9 +659,25 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze) {
     f.nty = (g.ny + ty - 1) / ty;
     f.nzc = (ze - zb + tz - 1) / tz;
     f.items = f.ntx * f.nty * f.nzc;
+    f.item0 = 0;
+    f.count = f.items;
     f.per_xcd = (f.items + NXCD - 1) / NXCD;
     f.blocks = f.per_xcd * NXCD;
     return f;
+}
+
+std::vector<FusedGrid> fused_windows(const FusedGrid &fg, int window) {
+    std::vector<FusedGrid> out;
+    if (window < NXCD) window = NXCD;
+    for (int i0 = 0; i0 < fg.items; i0 += window) {
+        FusedGrid w = fg;
+        w.item0 = i0;
+        w.count = std::min(window, fg.items - i0);
+        w.per_xcd = (w.count + NXCD - 1) / NXCD;
+        w.blocks = w.per_xcd * NXCD;
+        out.push_back(w);
+    }
+    return out;
 }
 
 namespace {

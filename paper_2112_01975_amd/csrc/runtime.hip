@@ -263,6 +263,11 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
                     zb = ze;
                 }
             }
+            // one launch per round of work items (one item per CU)
+            std::vector<FusedSeg> rounds;
+            for (const FusedSeg &sg : c->segs)
+                for (const FusedGrid &w : fused_windows(sg.fg, cus)) rounds.push_back({sg.fn, w});
+            c->segs = rounds;
             if (!c->segs.empty()) c->fused = c->segs[0].fn;
         }
     }
