@@ -32,6 +32,22 @@ namespace {
 
 constexpr int NXCD = 8;   // MI355X: 8 XCDs, workgroups dispatched round-robin
 
+// Populations the FP64 unmasked step keeps in LDS for three planes instead of pulling them
+// again when the plane is collided: the first NQ in library order with c_x and c_z nonzero
+// (row-misaligned pulls from the neighbouring planes: (1,0,+-1), (1,1,+-1)). NQ is what the LDS left
+// beside the rho / psi ring and the g planes holds (3 NQ x 512 doubles = 48 KB).
+constexpr int NQ = 4;
+constexpr int queued(int q) {
+    for (int i = 1; i < 27; ++i)
+        if (Lat<3>::c(i, 0) != 0 && Lat<3>::c(i, 2) != 0 && q-- == 0) return i;
+    return -1;
+}
+constexpr bool is_queued(int i) {
+    for (int q = 0; q < NQ; ++q)
+        if (queued(q) == i) return true;
+    return false;
+}
+
 // library index of the velocity (cx, cy, cz)
 constexpr int index3(int cx, int cy, int cz) {
     for (int i = 0; i < 27; ++i)
@@ -261,6 +277,12 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     __shared__ C s_rho[RING * HP];
     __shared__ C s_psi[RING * HP];
     __shared__ C s_gxy[2][2][HP];
+    // FP64 unmasked: NQ populations of the own node kept for three planes in LDS instead of
+    // re-pulled at collide time. Slot k % 3 holds plane z0 + k, written when that plane is
+    // pulled for staging and read when it is collided; each thread reads and writes only
+    // its own entries, so no barrier orders them.
+    constexpr bool LQ = REPULL && !MASK;
+    __shared__ C s_q[LQ ? 3 * NQ * NT : 1];
 
     // XCD-aware work item: consecutive items on one XCD are spatial neighbours
     const int b = blockIdx.x;
@@ -398,6 +420,12 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             pull_all<S, C, MM>(Ab, lm, si, zs, h);
             if constexpr (MM) fix(Ab, lm, qlo_at(si, zs), si, zs, h);
         }
+        if constexpr (LQ)
+            if (j >= 0)
+                static_for<0, NQ>([&](auto Q) {
+                    constexpr int q = decltype(Q)::value;
+                    s_q[(j * NQ + q) * NT + t] = h[queued(q)];
+                });
         const C gzn = stage(e_int, solid, (si.v[1][1] + zs[1]) / SB, h, m, slot, buf);
         if (has_halo) {
             C hh[27], mh[4];
@@ -449,6 +477,15 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                     const uint32_t lz = links_at(si, zsz);
                     pull_all<S, C, MASK>(Ab, lz, si, zsz, qa);
                     fix(Ab, lz, qlo_at(si, zsz), si, zsz, qa);
+                } else if constexpr (LQ) {
+                    static_for<0, 27>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (!is_queued(i)) qa[i] = pull<i, S, C, false>(Ab, 0u, si, zsz);
+                    });
+                    static_for<0, NQ>([&](auto Q) {
+                        constexpr int q = decltype(Q)::value;
+                        qa[queued(q)] = s_q[((k % 3) * NQ + q) * NT + t];
+                    });
                 } else {
                     pull_all<S, C, false>(Ab, 0u, si, zsz, qa);
                 }
@@ -552,6 +589,12 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         if constexpr (MM)
             if (need3 && !((l3 >> LINK_SELF) & 1u)) fix(Ab, l3, b3, si, zs3, qa);
         if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, (si.v[1][1] + zs3[1]) / SB, qa, ma, slot, buf);
+        if constexpr (LQ)
+            if (need3)
+                static_for<0, NQ>([&](auto Q) {
+                    constexpr int q = decltype(Q)::value;
+                    s_q[((k % 3) * NQ + q) * NT + t] = qa[queued(q)];
+                });
         __syncthreads();
         shift_windows(gzn, buf);
     };
