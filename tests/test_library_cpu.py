@@ -79,6 +79,9 @@ def _wall_rows(rows, q):
     (_wall_rows((0,), 0.0), "(0, 1]"),
     (_wall_rows((0,), 1.5), "(0, 1]"),
     (_wall_rows((10, 12), 1.0), "1.01"),          # row 11 cut on both sides at q = 1
+    (dict(lattice=1, nx=1400, ny=1400, nz=1400), "larger than 2^31"),
+    # 1025 x 1427^2 fits below 2^31 nodes, but not with its rows padded to 1056
+    (dict(lattice=1, nx=1025, ny=1427, nz=1427), "with its rows padded"),
 ])
 def test_create_rejects_bad_parameters_without_gpu(bad, msg):
     import paper_2112_01975_amd as P
