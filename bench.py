@@ -459,7 +459,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused3 (single-pass step)" if r32["fused"] else "collide-stream pass",
-                     "bytes_per_lup": bytes_lup, "launch_ms": r32["kernel_ms"]["step_kernel"]},
+                     "bytes_per_lup": bytes_lup, "launch_ms": r32["kernel_ms"]["step_kernel"],
+                     # the counted HBM bytes over the same launch time (null without a current profile)
+                     "traffic_GBs": (traffic / (r32["kernel_ms"]["step_kernel"] * 1e-3) / 1e9
+                                     if traffic else None),
+                     "traffic_frac": (traffic / (r32["kernel_ms"]["step_kernel"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic else None)},
         "useful_frac_step": r32["mlups"] * 1e6 * bytes_lup / (HBM_PEAK_GBS * 1e9),
         "attainable_copy_GBs": probe["GBs"],
         "mass_rel_drift_fp32": abs(t32[0] / r32["mass0"] - 1),
