@@ -39,7 +39,8 @@ def tangential_pressure(tensor: np.ndarray, lattice: int, nx: int, ny: int, nz: 
     tangential pressure per node, from lbm_pressure_tensor's output [D(D+1)/2][N]
     (components xx, yy, xy in 2D; xx, yy, zz, xy, xz, yz in 3D). In 3D the tangential
     pressure is the mean over the plane normal to the radius, (tr P - P_rr) / 2; at r = 0
-    it is tr P / D."""
+    it is tr P / D. Offsets from the centre are taken without periodic wrapping: the drop or
+    bubble must not cross the box boundary."""
     D = _dims_of(lattice)
     if centre is None:
         centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
