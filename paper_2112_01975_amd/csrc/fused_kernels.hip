@@ -32,6 +32,11 @@ namespace {
 
 constexpr int NXCD = 8;   // MI355X: 8 XCDs, workgroups dispatched round-robin
 
+// Cache policy of the population stores: non-temporal. The lattice written in a step is not
+// read again in that step, and streaming its lines through L2 leaves the room to the lines
+// that neighbouring tiles share (x edges, y halo) between their reads.
+constexpr int STORE_NT = 2;
+
 // Populations the FP64 unmasked step keeps in LDS for three planes instead of pulling them
 // again when the plane is collided: the first NQ in library order with c_x and c_z nonzero
 // (row-misaligned pulls from the neighbouring planes: (1,0,+-1), (1,1,+-1)). NQ is what the LDS left
@@ -85,10 +90,10 @@ template <class S> struct Lattice1 {
     }
     template <int i> __device__ __forceinline__ void store(unsigned voff, unsigned soff, S v) const {
         if constexpr (sizeof(S) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff + (unsigned)i * qsb, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff + (unsigned)i * qsb, STORE_NT);
         } else {
             using u2 = unsigned __attribute__((ext_vector_type(2)));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff + (unsigned)i * qsb, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff + (unsigned)i * qsb, STORE_NT);
         }
     }
     __device__ __forceinline__ S raw_load(unsigned voff, unsigned soff) const {
@@ -135,10 +140,10 @@ template <class S> struct Lattice2 {
     }
     static __device__ __forceinline__ void raw_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S v) {
         if constexpr (sizeof(S) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, STORE_NT);
         } else {
             using u2 = unsigned __attribute__((ext_vector_type(2)));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, STORE_NT);
         }
     }
 };
