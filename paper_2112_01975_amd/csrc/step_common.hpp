@@ -73,6 +73,11 @@ template <class T> __device__ __forceinline__ T ld_at(const T *__restrict__ base
 template <class T> __device__ __forceinline__ void st_at(T *__restrict__ base, unsigned idx, T v) {
     *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
 }
+// The same store with the non-temporal cache policy, for a lattice that the step writing it
+// does not read again (its lines then do not displace the ones being read from L2).
+template <class T> __device__ __forceinline__ void st_nt_at(T *__restrict__ base, unsigned idx, T v) {
+    __builtin_nontemporal_store(v, (T *)((char *)base + idx * (unsigned)sizeof(T)));
+}
 
 // Population i arriving at fluid node n whose source n - c_i is solid. Halfway bounce-back
 // returns the opposite post-collision population of n itself. With wall fractions lq

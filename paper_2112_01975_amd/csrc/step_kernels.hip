@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
             static_for<0, Lat<D>::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                st_at(B + i * g.qs, (unsigned)n, S(h[i]));
+                st_nt_at(B + i * g.qs, (unsigned)n, S(h[i]));
             });
         }
         }
