@@ -202,10 +202,11 @@ int lbm_eos_pressure(const lbm_params *p, const double *rho, int64_t n, double *
 int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa);
 
 /* Batched sweep: ncases independent simulations (each a full lbm_params,
- * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes) advanced by ONE persistent
- * kernel launch per lbm_batch_step call, captured in a HIP graph; each case is
- * owned by one workgroup that runs the whole step loop with workgroup barriers.
- * Tile shapes and workgroup sizes come from the built-in autotuner. */
+ * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes) advanced together: each step is
+ * one launch per phase covering every case, with each case split into blocks in
+ * proportion to its size, and chunks of steps are captured in a HIP graph that
+ * lbm_batch_step replays. Interpolated walls (link_q) are rejected with
+ * LBM_E_INVAL. lbm_batch_step checks every case for divergence at its end. */
 int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out);
 int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const double *u);
 int lbm_batch_step(lbm_batch *b, int64_t n);

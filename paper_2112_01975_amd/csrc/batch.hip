@@ -1,18 +1,17 @@
-// batch.hip -- many independent simulations of uneven sizes in ONE persistent launch.
+// batch.hip -- many independent simulations of uneven sizes advanced together.
 //
-// Each case (a full problem statement: lattice, EOS, T/Tc, kappa, tau, precision,
-// grid) is owned by one workgroup, which runs the whole step loop itself:
-//   phase 1: pull-gather every node of the case -> rho, signed psi, g = rho u^3
-//            into the case's field arrays;
-//   workgroup barrier;
-//   phase 2: two-ring Korteweg force from the fields, correction, product-form
-//            equilibria and LBGK (same device functions as the single-case kernels),
-//            written to the other lattice; workgroup barrier; swap.
-// Only workgroup barriers are used: no case waits on another workgroup, so every
-// workgroup finishes after its own step count. The precision branch is uniform per
-// workgroup. One launch of `chunk` steps is captured in a HIP graph at creation;
-// lbm_batch_step replays it. The workgroup size is picked by a small autotuner
-// (timed trial launches) and kept in an in-process cache keyed by the case list.
+// Each case is a full problem statement (lattice, EOS, T/Tc, kappa, tau, precision, grid).
+// A step of a case has two phases:
+//   phase 1: pull-gather every node -> rho, signed psi, g = rho u^3 into the case's fields;
+//   phase 2: two-ring Korteweg force from the fields, correction, product-form equilibria
+//            and LBGK (the same device functions as the single-case kernels), written to
+//            the other lattice.
+// Stepped design (default): one launch per phase (and lattice) and step covers every case,
+// each case split into blocks of kStepNodes nodes, so the cases of a sweep share all CUs;
+// the phases are ordered by the stream. Persistent design (LBM2P_BATCH_STEPPED=0): one
+// workgroup owns a case and runs its whole step loop with workgroup barriers only; its
+// workgroup size comes from a small autotuner (timed trial launches, cached per case list).
+// Either way a chunk of steps is captured once in a HIP graph that lbm_batch_step replays.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdlib.h>
@@ -48,98 +47,142 @@ struct CaseDesc {
 };
 
 // --------------------------------------------------------------- device part
+// phase 1 at node n: rho, signed psi and g = rho u^3 of the state in A into the case's fields
 template <int D, class S, class C>
-__device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, int parity) {
+__device__ __forceinline__ void phase1_node(const CaseDesc &cd, const Params<C> &p, const S *A, int n) {
     constexpr int Q = Lat<D>::Q;
-    const Geom g = cd.g;
+    const Geom &g = cd.g;
     const uint8_t *mask = cd.mask;
     C *frho = (C *)cd.frho, *fpsi = (C *)cd.fpsi, *fg = (C *)cd.fg;
+    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+    C rho, ga[3] = {C(0), C(0), C(0)};
+    if (mask && mask[n]) {
+        rho = wall_density(p, n);
+    } else {
+        C h[Q];
+        if (mask)
+            gather<D, S, C, true>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
+        else
+            gather<D, S, C, false>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
+        C sum, j[3];
+        moments_of<D, C>(h, sum, j);
+        rho = p.rho_ref + sum;
+        const C rinv = rcp(rho);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const C ua = j[a] * rinv;
+            ga[a] = rho * ua * ua * ua;
+        }
+    }
+    frho[n] = rho;
+    fpsi[n] = signed_psi(p.eos, rho);
+#pragma unroll
+    for (int a = 0; a < D; ++a) fg[a * g.N + n] = ga[a];
+}
+
+// phase 2 at fluid node n: force from the fields, correction, equilibria, LBGK; A -> B
+template <int D, class S, class C>
+__device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> &p, const S *A, S *B, int n) {
+    constexpr int Q = Lat<D>::Q;
+    const Geom &g = cd.g;
+    const uint8_t *mask = cd.mask;
+    const C *frho = (const C *)cd.frho, *fpsi = (const C *)cd.fpsi, *fg = (const C *)cd.fg;
+    if (mask && mask[n]) return;
+    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+    const Nbr<D> nb(g, x, y, z);
+    const C rho = frho[n], spc = fpsi[n];
+    C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
+    static_for<1, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
+        constexpr C w3 = C(3.0 * weight<D>(i));
+        const int n1 = nb.at(cx, cy, cz);
+        const int x2 = wrapi(x + 2 * cx, g.nx), y2 = wrapi(y + 2 * cy, g.ny);
+        const int z2 = D == 3 ? wrapi(z + 2 * cz, g.nz) : 0;
+        const int n2 = x2 + g.nx * (y2 + g.ny * z2);
+        const C p1 = fabs(fpsi[n1]), p2 = fabs(fpsi[n2]);
+        const C r1 = frho[n1], r2 = frho[n2];
+        const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
+        const C tc = w3 * (C(2) * r1 - r2);
+        static_for<0, D>([&](auto A_) {
+            constexpr int a = decltype(A_)::value;
+            constexpr int ca = Lat<D>::c(i, a);
+            if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
+            if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
+        });
+    });
+    C Sf[3] = {C(0), C(0), C(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+    C h[Q];
+    if (mask)
+        gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
+    else
+        gather<D, S, C, false>(A, g.qs, mask, nb, n, h);
+    C drho, j[3];
+    moments_of<D, C>(h, drho, j);
+    const C rinv = rcp(rho);
+    C u[3] = {C(0), C(0), C(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] = j[a] * rinv;
+    const C omega = omega_of(p, rho);
+    const C cf = (C(1) - C(0.5) * omega) * C(0.5);
+    C Phi[3] = {C(0), C(0), C(0)};
+    Phi[0] = cf * (fg[nb.at(1, 0, 0)] - fg[nb.at(-1, 0, 0)]);
+    Phi[1] = cf * (fg[g.N + nb.at(0, 1, 0)] - fg[g.N + nb.at(0, -1, 0)]);
+    if constexpr (D == 3) Phi[2] = cf * (fg[2 * g.N + nb.at(0, 0, 1)] - fg[2 * g.N + nb.at(0, 0, -1)]);
+    collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        st_at(B + i * g.qs, (unsigned)n, S(h[i]));
+    });
+}
+
+// the whole step loop of one case in one workgroup (persistent design)
+template <int D, class S, class C>
+__device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, int parity) {
     S *L0 = (S *)cd.A, *L1 = (S *)cd.B;
     for (int st = 0; st < nsteps; ++st) {
         const bool even = ((st + parity) & 1) == 0;
         const S *A = even ? L0 : L1;
         S *B = even ? L1 : L0;
-        // phase 1: fields of the current state
-        for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
-            const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
-            C rho, ga[3] = {C(0), C(0), C(0)};
-            if (mask && mask[n]) {
-                rho = wall_density(p, n);
-            } else {
-                C h[Q];
-                if (mask)
-                    gather<D, S, C, true>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
-                else
-                    gather<D, S, C, false>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
-                C sum, j[3];
-                moments_of<D, C>(h, sum, j);
-                rho = p.rho_ref + sum;
-                const C rinv = rcp(rho);
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const C ua = j[a] * rinv;
-                    ga[a] = rho * ua * ua * ua;
-                }
-            }
-            frho[n] = rho;
-            fpsi[n] = signed_psi(p.eos, rho);
-#pragma unroll
-            for (int a = 0; a < D; ++a) fg[a * g.N + n] = ga[a];
-        }
+        for (int n = threadIdx.x; n < cd.g.N; n += blockDim.x) phase1_node<D, S, C>(cd, p, A, n);
         __syncthreads();
-        // phase 2: collide and stream A -> B
-        for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
-            if (mask && mask[n]) continue;
-            const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
-            const Nbr<D> nb(g, x, y, z);
-            const C rho = frho[n], spc = fpsi[n];
-            C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
-            static_for<1, Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
-                constexpr C w3 = C(3.0 * weight<D>(i));
-                const int n1 = nb.at(cx, cy, cz);
-                const int x2 = wrapi(x + 2 * cx, g.nx), y2 = wrapi(y + 2 * cy, g.ny);
-                const int z2 = D == 3 ? wrapi(z + 2 * cz, g.nz) : 0;
-                const int n2 = x2 + g.nx * (y2 + g.ny * z2);
-                const C p1 = fabs(fpsi[n1]), p2 = fabs(fpsi[n2]);
-                const C r1 = frho[n1], r2 = frho[n2];
-                const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
-                const C tc = w3 * (C(2) * r1 - r2);
-                static_for<0, D>([&](auto A_) {
-                    constexpr int a = decltype(A_)::value;
-                    constexpr int ca = Lat<D>::c(i, a);
-                    if constexpr (ca == 1) { Fp[a] += tp; Fc[a] += tc; }
-                    if constexpr (ca == -1) { Fp[a] -= tp; Fc[a] -= tc; }
-                });
-            });
-            C Sf[3] = {C(0), C(0), C(0)};
-#pragma unroll
-            for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
-            C h[Q];
-            if (mask)
-                gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
-            else
-                gather<D, S, C, false>(A, g.qs, mask, nb, n, h);
-            C drho, j[3];
-            moments_of<D, C>(h, drho, j);
-            const C rinv = rcp(rho);
-            C u[3] = {C(0), C(0), C(0)};
-#pragma unroll
-            for (int a = 0; a < D; ++a) u[a] = j[a] * rinv;
-            const C omega = omega_of(p, rho);
-            const C cf = (C(1) - C(0.5) * omega) * C(0.5);
-            C Phi[3] = {C(0), C(0), C(0)};
-            Phi[0] = cf * (fg[nb.at(1, 0, 0)] - fg[nb.at(-1, 0, 0)]);
-            Phi[1] = cf * (fg[g.N + nb.at(0, 1, 0)] - fg[g.N + nb.at(0, -1, 0)]);
-            if constexpr (D == 3) Phi[2] = cf * (fg[2 * g.N + nb.at(0, 0, 1)] - fg[2 * g.N + nb.at(0, 0, -1)]);
-            collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
-            static_for<0, Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                st_at(B + i * g.qs, (unsigned)n, S(h[i]));
-            });
-        }
+        for (int n = threadIdx.x; n < cd.g.N; n += blockDim.x) phase2_node<D, S, C>(cd, p, A, B, n);
         __syncthreads();
+    }
+}
+
+// Stepped design: one launch per phase (and lattice) and step over every case at once,
+// each case split into blocks of work items in proportion to its size, so that the
+// cases of a sweep share all CUs instead of one workgroup each.
+struct Work {
+    int c, k, nk;   // case, block of the case, blocks of the case
+};
+constexpr int kStepBlock = 256, kStepNodes = 512;   // threads per block, nodes per block
+
+template <int D, int PHASE>
+__global__ __launch_bounds__(kStepBlock) void k_batch_phase(const CaseDesc *__restrict__ cases,
+                                                           const Work *__restrict__ work, int st,
+                                                           const int *__restrict__ parity) {
+    const Work w = work[blockIdx.x];
+    const CaseDesc cd = cases[w.c];
+    const bool even = ((st + parity[w.c]) & 1) == 0;
+    const int stride = w.nk * kStepBlock;
+    if (cd.fp64) {
+        const double *A = (const double *)(even ? cd.A : cd.B);
+        double *B = (double *)(even ? cd.B : cd.A);
+        for (int n = w.k * kStepBlock + threadIdx.x; n < cd.g.N; n += stride) {
+            if constexpr (PHASE == 1) phase1_node<D, double, double>(cd, cd.pd, A, n);
+            else phase2_node<D, double, double>(cd, cd.pd, A, B, n);
+        }
+    } else {
+        const float *A = (const float *)(even ? cd.A : cd.B);
+        float *B = (float *)(even ? cd.B : cd.A);
+        for (int n = w.k * kStepBlock + threadIdx.x; n < cd.g.N; n += stride) {
+            if constexpr (PHASE == 1) phase1_node<D, float, float>(cd, cd.pf, A, n);
+            else phase2_node<D, float, float>(cd, cd.pf, A, B, n);
+        }
     }
 }
 
@@ -184,6 +227,9 @@ struct lbm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int block = 256, chunk = 200;
+    bool stepped = true;             // stepped kernels over all cases; false: one workgroup per case
+    Work *d_work2 = nullptr, *d_work3 = nullptr;
+    int nw2 = 0, nw3 = 0;            // work items per lattice for the stepped kernels
     std::vector<int> initialized;
     std::string err;
 };
@@ -212,6 +258,21 @@ void free_batch(lbm_batch *b) {
 
 int launch(lbm_batch *b, int nsteps, int block) {
     const int nc = (int)b->host.size();
+    if (b->stepped) {
+        for (int st = 0; st < nsteps; ++st) {
+            if (b->nw2) hipLaunchKernelGGL((k_batch_phase<2, 1>), dim3(b->nw2), dim3(kStepBlock), 0, b->stream,
+                                           b->d_cases, b->d_work2, st, b->d_parity);
+            if (b->nw3) hipLaunchKernelGGL((k_batch_phase<3, 1>), dim3(b->nw3), dim3(kStepBlock), 0, b->stream,
+                                           b->d_cases, b->d_work3, st, b->d_parity);
+            if (b->nw2) hipLaunchKernelGGL((k_batch_phase<2, 2>), dim3(b->nw2), dim3(kStepBlock), 0, b->stream,
+                                           b->d_cases, b->d_work2, st, b->d_parity);
+            if (b->nw3) hipLaunchKernelGGL((k_batch_phase<3, 2>), dim3(b->nw3), dim3(kStepBlock), 0, b->stream,
+                                           b->d_cases, b->d_work3, st, b->d_parity);
+        }
+        if (nsteps & 1)
+            hipLaunchKernelGGL(k_flip_parity, dim3((nc + 255) / 256), dim3(256), 0, b->stream, b->d_parity, nc, nsteps);
+        return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+    }
     if (b->n2)
         hipLaunchKernelGGL(k_batch<2>, dim3(b->n2), dim3(block), 0, b->stream, b->d_cases, b->d_order, nc, nsteps,
                            b->d_parity);
@@ -315,6 +376,26 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
         return cx > cy;
     });
     for (int c = 0; c < ncases; ++c) (b->host[c].D == 2 ? b->n2 : b->n3) += 1;
+    // work items of the stepped kernels: each case in blocks of kStepNodes nodes, largest first
+    std::vector<Work> w2, w3;
+    for (int c : order) {
+        const int nk = std::max(1, (int)((b->host[c].g.N + kStepNodes - 1) / kStepNodes));
+        for (int k = 0; k < nk; ++k) (b->host[c].D == 2 ? w2 : w3).push_back(Work{c, k, nk});
+    }
+    b->nw2 = (int)w2.size();
+    b->nw3 = (int)w3.size();
+    if (b->nw2 && !(b->d_work2 = (Work *)dalloc(w2.size() * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    if (b->nw3 && !(b->d_work3 = (Work *)dalloc(w3.size() * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    if ((b->nw2 && hipMemcpy(b->d_work2, w2.data(), w2.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess) ||
+        (b->nw3 && hipMemcpy(b->d_work3, w3.data(), w3.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess)) {
+        free_batch(b);
+        return bfail(nullptr, LBM_E_HIP, "work list upload failed");
+    }
+    // LBM2P_BATCH_STEPPED=0: the persistent design (one workgroup per case)
+    {
+        const char *sv = getenv("LBM2P_BATCH_STEPPED");
+        b->stepped = !(sv && atoi(sv) == 0);
+    }
     std::vector<int> zero(ncases, 0);
     if (hipMemcpy(b->d_cases, b->host.data(), ncases * sizeof(CaseDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_order, order.data(), ncases * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -352,6 +433,7 @@ int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const doub
 }
 
 static int autotune(lbm_batch *b) {
+    if (b->stepped) return LBM_OK;   // fixed blocks of kStepBlock threads
     const std::string sig = signature(b);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

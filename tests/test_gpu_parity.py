@@ -316,7 +316,10 @@ def _sweep_cases(n, steps_len_lo=32, steps_len_hi=96):
     return out
 
 
-def test_batched_sweep_matches_single_runs_and_oracle():
+@pytest.mark.parametrize("stepped", ["1", "0"])
+def test_batched_sweep_matches_single_runs_and_oracle(stepped, monkeypatch):
+    # both designs: the stepped kernels over every case (default) and one workgroup per case
+    monkeypatch.setenv("LBM2P_BATCH_STEPPED", stepped)
     import paper_2112_01975_amd as P
     cases = _sweep_cases(10)
     plist = [c.params(1 if not sc.fp64 else 0, rv if not sc.fp64 else 0.0) for sc, c, _, rv in cases]
@@ -339,7 +342,9 @@ def test_batched_sweep_matches_single_runs_and_oracle():
         P.lbm_batch_destroy(b)
 
 
-def test_batched_mixed_lattices_and_masks():
+@pytest.mark.parametrize("stepped", ["1", "0"])
+def test_batched_mixed_lattices_and_masks(stepped, monkeypatch):
+    monkeypatch.setenv("LBM2P_BATCH_STEPPED", stepped)
     import paper_2112_01975_amd as P
     c2 = Case(2, 40, 30, a=0.02, T_reduced=0.8, rho_wall=0.9, mask=L.random_mask(40, 30, 1, 0.05, 3))
     c3 = Case(3, 20, 18, 16, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
