@@ -159,7 +159,7 @@ __device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, i
 struct Work {
     int c, k, nk;   // case, block of the case, blocks of the case
 };
-constexpr int kStepBlock = 256, kStepNodes = 512;   // threads per block, nodes per block
+constexpr int kStepBlock = 256, kStepNodes = 256;   // threads per block, nodes per block (one per thread)
 
 template <int D, int PHASE>
 __global__ __launch_bounds__(kStepBlock) void k_batch_phase(const CaseDesc *__restrict__ cases,
