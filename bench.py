@@ -138,8 +138,8 @@ def traffic_from_profile():
 def batch_sweep(P, torch, steps):
     """64 D2Q9 flat-interface cases, 4 x L with L log-spaced 128..2048 increasing with T/Tc in
     0.55..0.99 (vdW, kappa 0.02, a set for W = 4 at T/Tc = 0.55, tau 0.8; FP32 below T/Tc = 0.95,
-    FP64 above): one persistent launch per chunk of steps (HIP graph) against the same cases
-    stepped one by one through lbm_step."""
+    FP64 above): the batch (a HIP graph per chunk of steps, each step one launch per phase over
+    every case) against the same cases stepped one by one through lbm_step."""
     import lbm_inputs as L
     base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.55, 0.02, 0.8)
     a = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
