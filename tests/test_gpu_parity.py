@@ -366,6 +366,36 @@ def test_batched_mixed_lattices_and_masks(stepped, monkeypatch):
         P.lbm_batch_destroy(b)
 
 
+def test_batch_designs_agree_bit_for_bit(monkeypatch):
+    # the stepped kernels and the persistent design run the same per-node device functions in
+    # the same order, so every field agrees exactly: FP64 and FP32 cases, both lattices, a mask,
+    # an odd step count (a parity flip) split across a graph chunk and a remainder
+    import paper_2112_01975_amd as P
+    monkeypatch.setenv("LBM2P_BATCH_CHUNK", "16")
+    c2 = Case(2, 40, 30, a=0.02, T_reduced=0.8, rho_wall=0.9, mask=L.random_mask(40, 30, 1, 0.05, 3))
+    c2b = Case(2, 64, 16, a=0.02, T_reduced=0.8)
+    c3 = Case(3, 20, 18, 16, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rv2, rl2 = c2.coexistence()
+    rv3, rl3 = c3.coexistence()
+    inits = [L.drop(40, 30, 1, 8.0, rl2, rv2, 4.0, noise=1e-4, seed=5),
+             L.flat_slab(64, 16, 1, rl2, rv2, 4.0, noise=1e-4, seed=7),
+             L.drop(20, 18, 16, 5.0, rl3, rv3, 5.0, noise=1e-5, seed=6)]
+    plist = [c2.params(0), c2b.params(1, rv2), c3.params(1, rv3)]
+    out = {}
+    for stepped in ("1", "0"):
+        monkeypatch.setenv("LBM2P_BATCH_STEPPED", stepped)
+        b = P.lbm_batch_create(plist)
+        try:
+            for i, r0 in enumerate(inits):
+                P.lbm_batch_init_fields(b, i, r0)
+            P.lbm_batch_step(b, 37)
+            out[stepped] = [P.lbm_batch_moments(b, i, c.N, c.lattice)[:2] for i, c in enumerate((c2, c2b, c3))]
+        finally:
+            P.lbm_batch_destroy(b)
+    for (ra, Ua), (rb, Ub) in zip(out["1"], out["0"]):
+        assert np.array_equal(ra, rb) and np.array_equal(Ua, Ub)
+
+
 # ------------------------------------------------------------------ body force, per-node wall densities
 def _layered_channel(lattice, nx, H, g, tau=1.0, tr=0.77, nz=1):
     """vdW liquid below / vapour above between two-row walls (normal to y for D2Q9, to z
