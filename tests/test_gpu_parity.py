@@ -272,6 +272,27 @@ def test_fused_step_matches_two_pass_fp64(dims, masked, monkeypatch):
     assert abs(fused[2][0] / two[2][0] - 1) < 1e-14
 
 
+@pytest.mark.parametrize("precision,masked", [(0, False), (1, False), (0, True)])
+def test_fused_step_in_several_launch_windows_matches_two_pass(precision, masked, monkeypatch):
+    # 256 x 64 x 32 in z-chunks of 2 planes: 4 x 8 x 16 = 512 work items, more than one per CU,
+    # so each step is several launches of one item per CU (with a mask, per plane run)
+    nx, ny, nz = 256, 64, 32
+    mask = L.pillar_mask(nx, ny, nz, 4, 4, 5) if masked else None
+    case = Case(3, nx, ny, nz, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6,
+                rho_wall=0.0102306 if masked else 0.0, mask=mask)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(nx, ny, nz, 12.0, rl, rv, 5.0, centre=(100.0, 30.0, 16.0), noise=1e-5, seed=1009)
+    rref = rv if precision == 1 else 0.0
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "2")
+    fused = run_gpu(case, rho0, None, 20, precision=precision, rho_ref=rref)
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    two = run_gpu(case, rho0, None, 20, precision=precision, rho_ref=rref)
+    if precision == 0:
+        assert max_rel(fused[0], two[0]) < 1e-12 and np.abs(fused[1] - two[1]).max() < 1e-13
+    else:
+        assert max_rel(fused[0], two[0]) < 1e-5 and np.abs(fused[1] - two[1]).max() < 1e-6
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_step_plane_runs_match_two_pass(precision, monkeypatch):
     # solids in two separate z-bands (a slab at z = 30..31 and scattered nodes at z = 5):
