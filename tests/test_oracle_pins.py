@@ -349,6 +349,66 @@ def test_kappa_for_width_roundtrip():
     fl = T.Fluid(T.PR, 2 / 49, B21, 0.6, 1.0, 0.344)
     k = T.kappa_for_width(fl, 5.0)
     assert abs(T.interface_width(fl, k) - 5.0) < 1e-9
+    # (kappa/2) rho'^2 = dOmega makes W proportional to sqrt(kappa) exactly (eq interface_W)
+    assert abs(T.interface_width(fl, 4 * k) / T.interface_width(fl, k) - 2.0) < 1e-12
+
+
+def _sigma_width_ratio(fl, kappa=0.01, width=None):
+    """sigma W / (kappa (rho_l - rho_v)^2) from the oracle's surface tension and width."""
+    rv, rl, _ = T.coexistence(fl)
+    W = (width or T.interface_width)(fl, kappa)
+    return T.surface_tension(fl, kappa) * W / (kappa * (rl - rv) ** 2)
+
+
+def _planted_width(fl, kappa):
+    """A plausible mistake in the width: the peak of the excess grand potential taken as half
+    of what it is (e.g. a dropped factor 2 in (kappa/2) rho'^2 = dOmega)."""
+    rv, rl, _ = T.coexistence(fl)
+    mx, _ = T.max_excess(fl)
+    return (rl - rv) / math.sqrt(2.0 * (0.5 * mx) / kappa)
+
+
+@pytest.mark.parametrize("eos,a,om", [(T.VDW, A9, 0.0), (T.PR, 2 / 49, 0.344)])
+def test_interface_width_reaches_the_quartic_well_limit_near_critical(eos, a, om):
+    # Near T_c the excess grand potential is the quartic double well A (rho - rho_v)^2 (rho_l - rho)^2
+    # (Sec. 2.1 profile, Sec. 3.2). Then max|rho'| = sqrt(A/(8 kappa)) (rho_l - rho_v)^2 and
+    # sigma = sqrt(2 kappa A) (rho_l - rho_v)^3 / 6, so sigma W = (2/3) kappa (rho_l - rho_v)^2 for
+    # any A: the limit pins W (eq interface_W) against sigma, which the near-critical law pins.
+    ratios = [_sigma_width_ratio(T.Fluid(eos, a, B21, tr, 1.0, om)) for tr in (0.97, 0.99, 0.995, 0.999)]
+    assert all(r1 > r2 for r1, r2 in zip(ratios, ratios[1:])), ratios
+    assert ratios[-1] > 2 / 3
+    assert abs(ratios[2] - 2 / 3) < 1e-3 and abs(ratios[3] - 2 / 3) < 3e-4, ratios
+    # a planted factor error in the width misses the limit by far
+    bad = _sigma_width_ratio(T.Fluid(eos, a, B21, 0.995, 1.0, om), width=_planted_width)
+    assert abs(bad - 2 / 3) > 0.1
+
+
+@pytest.mark.parametrize("tr,w", [(0.8, 8.0), (0.9, 10.0)])
+def test_interface_width_matches_the_equilibrated_slab(tr, w):
+    # The oracle's equilibrated flat interface (D2Q9, quasi-1D, 20000 steps) has a width
+    # W = (rho_l - rho_v)/max|d rho/dx| (central differences) and a Kirkwood-Buff tension
+    # (integral of P_xx - P_yy of the discrete pressure tensor, Appendix E). Both exceed the
+    # second-gradient theory by ~19% (the discrete step acts as a capillary coefficient ~1.4
+    # times kappa~), but both scale as sqrt(kappa), so their ratio sigma/W is independent of
+    # the effective coefficient and must equal the theory's sigma/W.
+    fl0 = T.Fluid(T.VDW, A9, B21, tr)
+    a = A9 * 0.02 / T.kappa_for_width(fl0, w)
+    fl = T.Fluid(T.VDW, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    W, sig = T.interface_width(fl, 0.02), T.surface_tension(fl, 0.02)
+    assert abs(W - w) < 1e-9
+    n = int(20 * W) + int(20 * W) % 2
+    cfg = O.Config(2, n, 2, 1, T.VDW, a, B21, 1.0, 0.0, tr, 0.02, 0.8)
+    orc = O.Oracle(cfg).init(L.flat_slab(n, 2, 1, rl, rv, W))
+    orc.step(20000)
+    r = orc.moments()[0].reshape(2, n)[0]
+    w_sim = (r.max() - r.min()) / (np.abs(np.roll(r, -1) - np.roll(r, 1)) / 2).max()
+    Pt = orc.pressure_tensor()
+    sig_sim = float(np.sum(Pt[0].reshape(2, n)[0] - Pt[1].reshape(2, n)[0])) / 2   # two interfaces
+    assert 1.1 < w_sim / W < 1.3 and 1.1 < sig_sim / sig < 1.3
+    assert abs((sig_sim / w_sim) / (sig / W) - 1) < 0.025
+    bad = _planted_width(fl, 0.02)
+    assert abs((sig_sim / w_sim) / (sig / bad) - 1) > 0.2
 
 
 # ------------------------------------------------------------------ zero-force reduction
