@@ -7,7 +7,8 @@ product form (Sec. 2.3.2, eq prod) is an outer product of per-axis Psi triplets.
 The equation of state comes from thermo.Fluid.
 
 Step, with the readings used throughout the oracle: S = -F for the discrete
-Korteweg force of eq Kforce_final, xi* = u + S/rho, zeta* = 1/3 + xi*^2 + Phi/rho,
+Korteweg force of eq Kforce_final (or its Shan-Chen, dual-range or general
+stencil coefficients, Sec. 2.3.4), xi* = u + S/rho, zeta* = 1/3 + xi*^2 + Phi/rho,
 Phi = (1 - omega/2) d_a(rho u_a^3) by central differences, halfway bounce-back,
 or, when per-link wall distances are given, linearly interpolated bounce-back
 (Bouzidi et al., the wall scheme cited in Sec. 4.5).
@@ -21,6 +22,17 @@ import numpy as np
 from .thermo import Fluid
 
 AXIS_W = np.array([1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0])   # Psi_{-1,0,+1}(0, 1/3)
+
+
+def _stencil_pairs(model, kappa, g):
+    """((G1, G2), (G3, G4)) of the pseudo-potential and capillary rings (Sec. 2.3.4)."""
+    if model == 0:                       # eq Kforce_final
+        return (4.0 / 3.0, -1.0 / 6.0), (2.0 * kappa, -kappa)
+    if model == 1:                       # eq SCforce
+        return (1.0, 0.0), (0.0, 0.0)
+    if model == 2:                       # eq DRforce: eq PPcond1 only
+        return (g[0], (1.0 - g[0]) / 2.0), (0.0, 0.0)
+    return (g[0], g[1]), (g[2], g[3])
 
 
 def _velocities(D):
@@ -52,9 +64,10 @@ class BruteForce:
 
     def __init__(self, D, shape, fluid: Fluid, kappa, tau, rho_wall=0.0, mask=None,
                  tau_vapour=0.0, rho_liquid=0.0, rho_vapour=0.0, accel=(0.0, 0.0, 0.0), rho_wall_field=None,
-                 link_q=None):
+                 link_q=None, force_model=0, force_g=(0.0, 0.0, 0.0, 0.0)):
         self.D, self.shape = D, tuple(shape)
         self.fluid, self.kappa = fluid, kappa
+        self.gpsi, self.grho = _stencil_pairs(force_model, kappa, force_g)
         self.tau, self.tau_v, self.rl, self.rv = tau, tau_vapour, rho_liquid, rho_vapour
         # per-node wall densities if given (only solid entries matter), else one value
         self.rho_wall = rho_wall if rho_wall_field is None else np.asarray(rho_wall_field, float).reshape(shape)
@@ -100,13 +113,13 @@ class BruteForce:
         Fcap = np.zeros((D,) + self.shape)
         for c in self.vel:
             w3 = 3.0 * self.wcube[self._idx(c)]
-            tp = w3 * ((4.0 / 3.0) * _roll(psi, c, 1) - (1.0 / 6.0) * _roll(psi, c, 2))
-            tc = w3 * (2.0 * _roll(rho, c, 1) - _roll(rho, c, 2))
+            tp = w3 * (self.gpsi[0] * _roll(psi, c, 1) + self.gpsi[1] * _roll(psi, c, 2))
+            tc = w3 * (self.grho[0] * _roll(rho, c, 1) + self.grho[1] * _roll(rho, c, 2))
             for a in range(D):
                 if c[a]:
                     Fpsi[a] += c[a] * tp
                     Fcap[a] += c[a] * tc
-        F = 2.0 * sgn * psi * Fpsi + self.kappa * rho * Fcap
+        F = 2.0 * sgn * psi * Fpsi + rho * Fcap
         S = -F + np.stack([rho * g for g in self.accel])
         return np.where(self.solid, 0.0, S)
 
@@ -184,8 +197,9 @@ class BruteForce:
                 cap1 += weight * _roll(rho, c, 1)
                 cap2 += weight * _roll(rho, c, 2)
                 capx += weight * _roll(rho, c, -1) * _roll(rho, c, 1)
-            nonlocal_ = (-sgn * (8.0 / 6.0) * psi * ring1 + sgn / 6.0 * (psi * ring2 + across)
-                         - self.kappa * rho * cap1 + 0.5 * self.kappa * (rho * cap2 + capx))
+            (g1, g2), (g3, g4) = self.gpsi, self.grho
+            nonlocal_ = (-sgn * g1 * psi * ring1 - sgn * g2 * (psi * ring2 + across)
+                         - 0.5 * g3 * rho * cap1 - 0.5 * g4 * (rho * cap2 + capx))
             out.append(np.where(self.solid, 0.0, flux - nonlocal_).ravel())
         return np.stack(out)
 

@@ -15,6 +15,10 @@
  *      Sec. 2.3), pseudo-potential psi = sqrt|P - P0| and its sign (eq force_form);
  *   3. discrete Korteweg force (eq Kforce_final): pseudo-potential pair
  *      G1 = 4/3, G2 = -1/6 (eqs PPcond1, PPcond2) and capillary pair (2, -1) kappa;
+ *      the same two-ring stencils with other coefficients give the single-ring
+ *      Shan-Chen force (G2 = 0, no capillary term, eq SCforce) and the dual-range
+ *      force (only eq PPcond1 imposed, eq DRforce), the special cases the paper
+ *      discusses after eq Kforce_final;
  *   4. momentum source S = -F (reading: the kinetic model eq gen_kinetic_model_ext
  *      enters the force with a minus sign; the literal sign is kept as a test-only
  *      variant);
@@ -56,6 +60,12 @@ typedef struct {
                                node n whose link n -> n + c_i ends in a solid node, the wall's
                                fractional distance q in (0, 1] along that link (interpolated
                                bounce-back, Sec. 4.5); NULL = halfway, q = 1/2 (copied) */
+    int force_model;        /* stencil coefficients (G1, G2) of eq PP_discrete and (G3, G4) of
+                               eq capillary_discrete: 0 eq Kforce_final (4/3, -1/6, 2 kappa,
+                               -kappa); 1 single-ring Shan-Chen force eq SCforce (1, 0, 0, 0);
+                               2 dual-range force eq DRforce (force_g[0], (1 - force_g[0])/2,
+                               0, 0); 3 all four from force_g */
+    double force_g[4];
 } orc_params;
 
 typedef struct {
@@ -66,6 +76,7 @@ typedef struct {
     double w[27];
     int opp[27];
     double T, aalpha;
+    double G[4];            /* stencil coefficients G1..G4 of eqs PP_discrete, capillary_discrete */
     unsigned char *mask;    /* NULL = fully periodic */
     double *rho_wf;         /* NULL or [N]: per-node wall density */
     double *lq, *fpost;     /* interpolated bounce-back: [Q][N] link distances, post-collision */
@@ -206,6 +217,26 @@ static double omega_at(const orc_ctx *x, double rho)
     return 1.0 / (3.0 * nu + 0.5);
 }
 
+/* Coefficients of the two-ring stencils (Sec. 2.3.4). The pseudo-potential pair (G1, G2) of
+ * eq PP_discrete and the capillary pair (G3, G4) of eq capillary_discrete, the latter
+ * including kappa~:
+ *   Korteweg (eq Kforce_final): G1 + 2 G2 = 1 (eq PPcond1) and G1 + 8 G2 = 0 (eq PPcond2)
+ *     give (4/3, -1/6); the capillary pair is (2, -1) kappa~;
+ *   Shan-Chen (eq SCforce): G2 = 0 and G3 = G4 = 0, so G1 = 1 by eq PPcond1;
+ *   dual range (eq DRforce): eq PPcond1 alone, G2 = (1 - G1)/2, no capillary pair;
+ *   general: the four values as given.
+ * Returns nonzero for an unknown model. */
+static int stencil_coefficients(const orc_params *p, double G[4])
+{
+    switch (p->force_model) {
+    case 0: G[0] = 4.0 / 3.0; G[1] = -1.0 / 6.0; G[2] = 2.0 * p->kappa; G[3] = -p->kappa; return 0;
+    case 1: G[0] = 1.0; G[1] = 0.0; G[2] = 0.0; G[3] = 0.0; return 0;
+    case 2: G[0] = p->force_g[0]; G[1] = 0.5 * (1.0 - p->force_g[0]); G[2] = 0.0; G[3] = 0.0; return 0;
+    case 3: for (int k = 0; k < 4; ++k) G[k] = p->force_g[k]; return 0;
+    default: return 1;
+    }
+}
+
 /* ---- lifecycle ---- */
 void orc_destroy(void *h)
 {
@@ -231,6 +262,7 @@ void *orc_create(const orc_params *p, const unsigned char *mask)
     x->N = (long)p->nx * p->ny * p->nz;
     x->T = p->T_reduced * crit_temperature(p);
     x->aalpha = p->a * alpha_T(p);
+    if (stencil_coefficients(p, x->G)) { orc_destroy(x); return NULL; }
     long N = x->N;
     x->f = (double *)calloc((size_t)x->Q * N, sizeof(double));
     x->fn = (double *)calloc((size_t)x->Q * N, sizeof(double));
@@ -291,12 +323,57 @@ int orc_init(void *h, const double *rho0, const double *U0)
 /* virtual density of solid node n (Sec. 4.5): per node if given, else rho_wall */
 static double wall_rho(const orc_ctx *x, long n) { return x->rho_wf ? x->rho_wf[n] : x->p.rho_wall; }
 
+/* step 2 for every node: psi = sqrt|P - P0| and the sign of P - P0 (eq force_form) of the
+ * density field x->rho */
+static void pseudo_potential(orc_ctx *x)
+{
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < x->N; ++n) {
+        double r = x->rho[n], P = eos_pressure(x, r), P0 = r / 3.0;
+        x->psi[n] = sqrt(fabs(P - P0));
+        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
+    }
+}
+
+/* step 3 at node n: the discrete force of eq Kforce_final (with the stencil pairs of
+ * eqs PP_discrete and capillary_discrete) from x->psi, x->sgn and x->rho,
+ *   F = s 2 psi(r) sum_i 3 w_i c_i [G1 psi(r + c_i) + G2 psi(r + 2 c_i)]
+ *     + rho(r) sum_i 3 w_i c_i [G3 rho(r + c_i) + G4 rho(r + 2 c_i)],   3 w_i = w_i / cs^2 */
+static void force_at(const orc_ctx *x, long n, double F[3])
+{
+    const double *G = x->G;
+    double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
+    for (int i = 0; i < x->Q; ++i) {
+        long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
+        double wp = 3.0 * x->w[i] * (G[0] * x->psi[n1] + G[1] * x->psi[n2]);
+        double wc = 3.0 * x->w[i] * (G[2] * x->rho[n1] + G[3] * x->rho[n2]);
+        for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
+    }
+    for (int a = 0; a < 3; ++a) F[a] = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->rho[n] * Fc[a];
+}
+
+/* step 4 for every node: momentum source S = -F + rho g (reading of the force sign), zero at
+ * solid nodes and beyond the lattice dimension */
+static void source(orc_ctx *x)
+{
+    long N = x->N;
+    const orc_params *p = &x->p;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double F[3];
+        force_at(x, n, F);
+        for (int a = 0; a < 3; ++a) {
+            double s = ((p->variant & 2) ? F[a] : -F[a]) + x->rho[n] * p->accel[a];
+            x->S[a * N + n] = (solid(x, n) || a >= x->D) ? 0.0 : s;
+        }
+    }
+}
+
 /* steps 1-4: moments, EOS, pseudo-potential, g = rho u^3, source S = -F_K + rho g */
 static void fields(orc_ctx *x)
 {
     long N = x->N;
     int D = x->D, Q = x->Q;
-    const orc_params *p = &x->p;
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         double r, j[3] = {0, 0, 0};
@@ -316,52 +393,17 @@ static void fields(orc_ctx *x)
             x->u[a * N + n] = (a < D) ? ua : 0.0;
             x->g[a * N + n] = (a < D) ? r * ua * ua * ua : 0.0;
         }
-        double P = eos_pressure(x, r), P0 = r / 3.0;
-        x->psi[n] = sqrt(fabs(P - P0));
-        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
     }
-#pragma omp parallel for schedule(static)
-    for (long n = 0; n < N; ++n) {
-        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
-        for (int i = 0; i < Q; ++i) {
-            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
-            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
-            double wc = 3.0 * x->w[i] * (2.0 * x->rho[n1] - x->rho[n2]);
-            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
-        }
-        for (int a = 0; a < 3; ++a) {
-            double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + p->kappa * x->rho[n] * Fc[a];
-            double s = ((p->variant & 2) ? F : -F) + x->rho[n] * p->accel[a];
-            x->S[a * N + n] = (solid(x, n) || a >= D) ? 0.0 : s;
-        }
-    }
+    pseudo_potential(x);
+    source(x);
 }
 
 /* steps 2-4 for a given density field (solid nodes read as rho_w): x->S = -F_K */
 static void source_of_density(orc_ctx *x, const double *rho)
 {
-    long N = x->N;
-    for (long n = 0; n < N; ++n) {
-        double r = solid(x, n) ? wall_rho(x, n) : rho[n];
-        x->rho[n] = r;
-        double P = eos_pressure(x, r), P0 = r / 3.0;
-        x->psi[n] = sqrt(fabs(P - P0));
-        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
-    }
-    for (long n = 0; n < N; ++n) {
-        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
-        for (int i = 0; i < x->Q; ++i) {
-            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
-            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
-            double wc = 3.0 * x->w[i] * (2.0 * x->rho[n1] - x->rho[n2]);
-            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
-        }
-        for (int a = 0; a < 3; ++a) {
-            double F = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * x->rho[n] * Fc[a];
-            double s = ((x->p.variant & 2) ? F : -F) + x->rho[n] * x->p.accel[a];
-            x->S[a * N + n] = (solid(x, n) || a >= x->D) ? 0.0 : s;
-        }
-    }
+    for (long n = 0; n < x->N; ++n) x->rho[n] = solid(x, n) ? wall_rho(x, n) : rho[n];
+    pseudo_potential(x);
+    source(x);
 }
 
 /* steps 5-7 at one node: f -> f_post; S and Phi given; returns rho via *rho_out */
@@ -514,27 +556,19 @@ void orc_source(void *h, double *S)
     memcpy(S, x->S, sizeof(double) * 3 * (size_t)x->N);
 }
 
-/* F_K of eq Kforce_final for a given density field (all nodes read as given) */
+/* F_K of eq Kforce_final for a given density field (all nodes read as given, solid or not);
+ * overwrites the context's density and pseudo-potential fields, which the next step
+ * recomputes from the populations */
 void orc_korteweg_force(void *h, const double *rho, double *F)
 {
     orc_ctx *x = (orc_ctx *)h;
     long N = x->N;
-    int Q = x->Q;
+    memcpy(x->rho, rho, sizeof(double) * (size_t)N);
+    pseudo_potential(x);
     for (long n = 0; n < N; ++n) {
-        double P = eos_pressure(x, rho[n]), P0 = rho[n] / 3.0;
-        x->psi[n] = sqrt(fabs(P - P0));
-        x->sgn[n] = (P > P0) ? 1.0 : -1.0;
-    }
-    for (long n = 0; n < N; ++n) {
-        double Fp[3] = {0, 0, 0}, Fc[3] = {0, 0, 0};
-        for (int i = 0; i < Q; ++i) {
-            long n1 = nbr(x, n, 1, x->c[i]), n2 = nbr(x, n, 2, x->c[i]);
-            double wp = 3.0 * x->w[i] * ((4.0 / 3.0) * x->psi[n1] - (1.0 / 6.0) * x->psi[n2]);
-            double wc = 3.0 * x->w[i] * (2.0 * rho[n1] - rho[n2]);
-            for (int a = 0; a < 3; ++a) { Fp[a] += x->c[i][a] * wp; Fc[a] += x->c[i][a] * wc; }
-        }
-        for (int a = 0; a < 3; ++a)
-            F[a * N + n] = x->sgn[n] * 2.0 * x->psi[n] * Fp[a] + x->p.kappa * rho[n] * Fc[a];
+        double Fn[3];
+        force_at(x, n, Fn);
+        for (int a = 0; a < 3; ++a) F[a * N + n] = Fn[a];
     }
 }
 
@@ -545,11 +579,13 @@ void orc_korteweg_force(void *h, const double *rho, double *F)
  * reading S = -F of the momentum source, the momentum flux that the tensors complete is
  * P = Pi - (P^A + P^B + P^C + P^D), where Pi_ab = sum_i c_ia c_ib f_i is the second moment of
  * the node's pre-collision populations (the lattice momentum flux; rho/3 only without a
- * force). Per node, with 3 w_i = w_i / cs^2 and s the sign of P - P0:
- *   P^A = -s (8/6) psi(r) sum 3w c c psi(r + c)
- *   P^B = +s (1/6) [psi(r) sum 3w c c psi(r + 2c) + sum 3w c c psi(r - c) psi(r + c)]
- *   P^C = -kappa rho(r) sum 3w c c rho(r + c)
- *   P^D = (kappa/2) [rho(r) sum 3w c c rho(r + 2c) + sum 3w c c rho(r - c) rho(r + c)]
+ * force). Per node, with 3 w_i = w_i / cs^2 and s the sign of P - P0, for the stencil pairs
+ * (G1, G2) and (G3, G4) of the force (printed for (4/3, -1/6) and (2, -1) kappa, where the
+ * factors are 8/6, -1/6, kappa and -kappa/2; each part is linear in its coefficient):
+ *   P^A = -s G1 psi(r) sum 3w c c psi(r + c)
+ *   P^B = -s G2 [psi(r) sum 3w c c psi(r + 2c) + sum 3w c c psi(r - c) psi(r + c)]
+ *   P^C = -(G3/2) rho(r) sum 3w c c rho(r + c)
+ *   P^D = -(G4/2) [rho(r) sum 3w c c rho(r + 2c) + sum 3w c c rho(r - c) rho(r + c)]
  * Solid nodes enter psi and rho with the wall density, as in the force. */
 void orc_pressure_tensor(void *h, double *out)
 {
@@ -583,11 +619,12 @@ void orc_pressure_tensor(void *h, double *out)
                 sD1 += cc * x->rho[p2];
                 sD2 += cc * x->rho[m1] * x->rho[p1];
             }
-            const double s = x->sgn[n], psi = x->psi[n], r = x->rho[n], kap = x->p.kappa;
-            const double PA = -s * (8.0 / 6.0) * psi * sA;
-            const double PB = s * (1.0 / 6.0) * (psi * sB1 + sB2);
-            const double PC = -kap * r * sC;
-            const double PD = 0.5 * kap * (r * sD1 + sD2);
+            const double s = x->sgn[n], psi = x->psi[n], r = x->rho[n];
+            const double *G = x->G;
+            const double PA = -s * G[0] * psi * sA;
+            const double PB = -s * G[1] * (psi * sB1 + sB2);
+            const double PC = -0.5 * G[2] * r * sC;
+            const double PD = -0.5 * G[3] * (r * sD1 + sD2);
             out[k * N + n] = pi - (PA + PB + PC + PD);
         }
     }

@@ -161,6 +161,83 @@ def test_capillary_stencil_is_second_order(D, axis):
     assert 3.6 < e1 / e2 < 4.4
 
 
+def _spectral_derivatives(f, n):
+    """First and third derivatives of one period of a smooth periodic sample (FFT)."""
+    k = 2 * math.pi * np.fft.fftfreq(n, d=1.0)
+    fh = np.fft.fft(f)
+    return np.real(np.fft.ifft(1j * k * fh)), np.real(np.fft.ifft(-1j * k ** 3 * fh))
+
+
+def _pseudo_potential_force_error(D, n, axis, model, g1, coeff):
+    """Relative error of the oracle's force on a sinusoidal density (one period over n nodes
+    along `axis`) against s [2 psi psi' + coeff psi psi'''] with exact (spectral) derivatives
+    of psi = sqrt|P - P0|; vdW at T/Tc = 0.9 with rho in [2.7, 3.3], where P < P0 (s = -1)."""
+    dims = [3, 3, 3 if D == 3 else 1]
+    dims[axis] = n
+    nx, ny, nz = dims
+    cfg = O.Config(D, nx, ny, nz, T.VDW, 0.02, B21, 1.0, 0.0, 0.9, 0.05, force_model=model,
+                   force_g=(g1, 0.0, 0.0, 0.0))
+    orc = O.Oracle(cfg)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = [x, y, z][axis].ravel().astype(float)
+    rho = 3.0 + 0.3 * np.sin(2 * math.pi * s / n)
+    F = orc.korteweg_force(rho)[axis]
+    fl = cfg.fluid()
+    line = 3.0 + 0.3 * np.sin(2 * math.pi * np.arange(n) / n)
+    d = fl.pressure(line) - line / 3.0
+    assert np.all(d < 0)
+    psi_line = np.sqrt(-d)
+    d1, d3 = _spectral_derivatives(psi_line, n)
+    j = s.astype(int)
+    psi, p1, p3 = psi_line[j], d1[j], d3[j]
+    exact = -(2 * psi * p1 + coeff * psi * p3)
+    return np.abs(F - exact).max() / np.abs(exact).max()
+
+
+@pytest.mark.parametrize("D,axis", [(2, 0), (2, 1), (3, 2)])
+def test_shan_chen_force_retains_the_third_order_term(D, axis):
+    # eq SCforce: with G2 = 0 and no capillary pair, eq PPcond1 gives G1 = 1 and the stencil
+    # carries psi grad lap psi with coefficient 1/3: against that expansion the residual is
+    # fourth order (error x16 per halving of h); without the term it would be second order
+    e1 = _pseudo_potential_force_error(D, 24, axis, O.FORCE_SHAN_CHEN, 0.0, 1 / 3)
+    e2 = _pseudo_potential_force_error(D, 48, axis, O.FORCE_SHAN_CHEN, 0.0, 1 / 3)
+    assert 13.0 < e1 / e2 < 19.0, (e1, e2)
+    w1 = _pseudo_potential_force_error(D, 24, axis, O.FORCE_SHAN_CHEN, 0.0, 0.0)
+    w2 = _pseudo_potential_force_error(D, 48, axis, O.FORCE_SHAN_CHEN, 0.0, 0.0)
+    assert 3.6 < w1 / w2 < 4.4
+
+
+@pytest.mark.parametrize("g1", [0.8, 1.2, 2.0])
+def test_dual_range_force_third_order_coefficient(g1):
+    # eq DRforce: eq PPcond1 alone (G2 = (1 - G1)/2) leaves psi grad lap psi with the
+    # coefficient 4/3 - G1
+    e1 = _pseudo_potential_force_error(3, 24, 0, O.FORCE_DUAL_RANGE, g1, 4 / 3 - g1)
+    e2 = _pseudo_potential_force_error(3, 48, 0, O.FORCE_DUAL_RANGE, g1, 4 / 3 - g1)
+    assert 13.0 < e1 / e2 < 19.0, (e1, e2)
+    # the Korteweg pair's coefficients (4/3 - G1 = 0 at G1 = 4/3 with G2 = -1/6) are the
+    # dual-range model at G1 = 4/3
+    k = _pseudo_potential_force_error(3, 24, 0, O.FORCE_DUAL_RANGE, 4 / 3, 0.0)
+    assert k < 2e-4
+
+
+def test_general_stencil_coefficients_reproduce_each_model():
+    # force model 3 takes the four coefficients as given: the Korteweg, Shan-Chen and
+    # dual-range coefficient sets reproduce those models' forces exactly
+    n, kappa = 16, 0.05
+    rho = 3.0 + 0.3 * np.sin(2 * math.pi * np.arange(n * 9) / 37.0)
+    ref = {}
+    for model, g, G in ((O.FORCE_KORTEWEG, 0.0, (4 / 3, -1 / 6, 2 * kappa, -kappa)),
+                        (O.FORCE_SHAN_CHEN, 0.0, (1.0, 0.0, 0.0, 0.0)),
+                        (O.FORCE_DUAL_RANGE, 0.9, (0.9, 0.05, 0.0, 0.0))):
+        a = O.Oracle(O.Config(2, n, 9, 1, T.VDW, 0.02, B21, 1.0, 0.0, 0.9, kappa, force_model=model,
+                              force_g=(g, 0.0, 0.0, 0.0))).korteweg_force(rho)
+        b = O.Oracle(O.Config(2, n, 9, 1, T.VDW, 0.02, B21, 1.0, 0.0, 0.9, kappa, force_model=O.FORCE_GENERAL,
+                              force_g=G)).korteweg_force(rho)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()   # (1 - 0.9)/2 rounds differently from 0.05
+        ref[model] = a
+    assert np.abs(ref[O.FORCE_KORTEWEG] - ref[O.FORCE_SHAN_CHEN]).max() > 1e-3
+
+
 # ------------------------------------------------------------------ EOS and Maxwell
 def test_vdw_critical_point():
     fl = T.Fluid(T.VDW, A9, B21, 1.0)
@@ -458,6 +535,35 @@ def test_oracle_matches_independent_numpy_step(D, zyx, eos, a, om, masked):
     r2, U2 = bf.init(rho, u).step(10).moments()
     assert np.abs(r1 - r2).max() < 1e-13 * np.abs(r2).max()
     assert np.abs(U1 - U2).max() < 1e-13
+
+
+@pytest.mark.parametrize("D,model,g,eos", [(2, O.FORCE_SHAN_CHEN, (0, 0, 0, 0), T.SC1),
+                                           (3, O.FORCE_SHAN_CHEN, (0, 0, 0, 0), T.VDW),
+                                           (2, O.FORCE_DUAL_RANGE, (1.1, 0, 0, 0), T.PR),
+                                           (3, O.FORCE_DUAL_RANGE, (0.9, 0, 0, 0), T.SC2),
+                                           (3, O.FORCE_GENERAL, (1.2, -0.1, 0.03, -0.02), T.VDW)])
+def test_oracle_matches_numpy_step_with_other_force_models(D, model, g, eos):
+    # the Shan-Chen, dual-range and general stencil coefficients through the full step, with
+    # a mask and two viscosities, against the separately written NumPy step
+    nx, ny, nz = (6, 5, 4) if D == 3 else (7, 6, 1)
+    a, om = {T.VDW: (0.02, 0.0), T.PR: (0.005, 0.344), T.SC1: (0.0, 0.0), T.SC2: (0.0, 0.0)}[eos]
+    fl = T.Fluid(eos, a, B21, 0.7, 1.0, om)
+    rv, rl, _ = T.coexistence(fl)
+    rho, u = L.random_state(nx * ny * nz, D, rv, rl, 0.05, 13)
+    mask = L.random_mask(nx, ny, nz, 0.12, 5)
+    cfg = O.Config(D, nx, ny, nz, eos, a, B21, 1.0, om, 0.7, 0.02, 0.8, 0.65, rl, rv, rho_wall=rv,
+                   force_model=model, force_g=g)
+    r1, U1, _ = O.Oracle(cfg, mask).init(rho, u).step(10).moments()
+    shape = (ny, nx) if D == 2 else (nz, ny, nx)
+    bf = B.BruteForce(D, shape, fl, 0.02, 0.8, rho_wall=rv, mask=mask, tau_vapour=0.65, rho_liquid=rl,
+                      rho_vapour=rv, force_model=model, force_g=g)
+    r2, U2 = bf.init(rho, u).step(10).moments()
+    assert np.abs(r1 - r2).max() < 1e-13 * np.abs(r2).max()
+    assert np.abs(U1 - U2).max() < 1e-13
+    # and the model matters: the Korteweg step from the same state differs
+    r3, _, _ = O.Oracle(O.Config(D, nx, ny, nz, eos, a, B21, 1.0, om, 0.7, 0.02, 0.8, 0.65, rl, rv, rho_wall=rv),
+                        mask).init(rho, u).step(10).moments()
+    assert np.abs(r3 - r1).max() > 1e-6 * np.abs(r1).max()
 
 
 # ------------------------------------------------------------------ invariants
@@ -874,6 +980,25 @@ def test_flat_interface_normal_pressure_is_uniform(D):
     nonlocal_ = flux - Pxx
     assert (np.ptp(r / 3 - nonlocal_) / pb) > 0.2
     assert abs((r[0] / 3 + nonlocal_[0]) / pb - 1) > 1.0
+
+
+@pytest.mark.parametrize("eos,a,tr,model,g", [(T.SC1, 0.0, 0.9, O.FORCE_SHAN_CHEN, (0, 0, 0, 0)),
+                                              (T.VDW, 0.02, 0.8, O.FORCE_DUAL_RANGE, (1.1, 0, 0, 0)),
+                                              (T.VDW, 0.02, 0.8, O.FORCE_GENERAL, (1.2, -0.1, 0.04, -0.02))])
+def test_flat_interface_normal_pressure_is_uniform_for_other_force_models(eos, a, tr, model, g):
+    # Appendix E's tensors scale with their stencil coefficients: with (G1, G2) obeying
+    # eq PPcond1 and (G3, G4) eq Ccond1 the discrete normal pressure is again uniform across
+    # an equilibrated flat interface and equals the bulk pressure
+    fl = T.Fluid(eos, a, B21, tr)
+    rv, rl, _ = T.coexistence(fl)
+    n = 64
+    cfg = O.Config(2, n, 1, 1, eos, a, B21, 1.0, 0.0, tr, 0.02, 0.8, force_model=model, force_g=g)
+    o = O.Oracle(cfg).init(L.flat_slab(n, 1, 1, rl, rv, 4.0)).step(30000)
+    r, _, _ = o.moments()
+    Pxx = o.pressure_tensor()[0]
+    pb = fl.pressure(r[0])
+    assert np.ptp(Pxx) < 3e-6 * abs(pb)
+    assert abs(Pxx.mean() / pb - 1) < 1e-3
 
 
 def test_kirkwood_buff_tension_equals_laplace_tension():
