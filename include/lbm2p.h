@@ -50,6 +50,17 @@ enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
  * the acentric factor are not used. */
 enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_RKS = 2, LBM_EOS_CS = 3, LBM_EOS_IDEAL = 4,
        LBM_EOS_SC1 = 5, LBM_EOS_SC2 = 6 };
+/* Stencil coefficients of the non-ideal force (Sec. 2.3.4): the pseudo-potential ring
+ * pair (G1, G2) of eq PP_discrete and the capillary pair (G3, G4) of eq capillary_discrete,
+ *   dt F = s 2 psi(r) sum_i (w_i/cs^2) c_i [G1 psi(r + c_i) + G2 psi(r + 2 c_i)]
+ *        + rho(r) sum_i (w_i/cs^2) c_i [G3 rho(r + c_i) + G4 rho(r + 2 c_i)]
+ * with s the sign of P - P0 (eq force_form), and the momentum source S = -F + rho g.
+ * LBM_FORCE_KORTEWEG: eq Kforce_final, (4/3, -1/6, 2 kappa, -kappa) (the default);
+ * LBM_FORCE_SHAN_CHEN: the single-ring force of eq SCforce, (1, 0, 0, 0): kappa unused;
+ * LBM_FORCE_DUAL_RANGE: the dual-range force of eq DRforce, G1 = force_g[0],
+ *   G2 = (1 - G1)/2 (eq PPcond1 only), no capillary pair: kappa unused;
+ * LBM_FORCE_GENERAL: G1..G4 = force_g[0..3] as given (G3, G4 carry any kappa). */
+enum { LBM_FORCE_KORTEWEG = 0, LBM_FORCE_SHAN_CHEN = 1, LBM_FORCE_DUAL_RANGE = 2, LBM_FORCE_GENERAL = 3 };
 /* LBM_FP64: populations stored and updated in FP64.
  * LBM_FP32_DEV: populations stored as FP32 deviations h_i = f_i - w_i rho_ref and
  * updated in FP32; mass and momentum reductions stay FP64. */
@@ -93,9 +104,15 @@ typedef struct {
                                Sec. 5.3) instead of halfway bounce-back (q = 1/2 gives the
                                same step). Needs a mask; a node cut on two opposite links
                                with q, q' >= 1/2 needs 1/(2q) + 1/(2q') >= 1.01 (the
-                               initial state is otherwise not representable). Such
-                               contexts take the two-pass step; lbm_batch_create rejects
-                               it. Copied at create */
+                               initial state is otherwise not representable). D3Q27
+                               contexts take the single-pass interpolating kernel on
+                               planes within three planes of a solid node (the two-pass
+                               step when the single-pass step is not available for the
+                               grid); D2Q9 takes the two-pass step; lbm_batch_create
+                               rejects it. Copied at create */
+    int force_model;        /* LBM_FORCE_* (0: eq Kforce_final) */
+    double force_g[4];      /* coefficients for LBM_FORCE_DUAL_RANGE ([0] = G1) and
+                               LBM_FORCE_GENERAL (G1..G4); finite */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

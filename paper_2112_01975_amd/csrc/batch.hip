@@ -1,6 +1,6 @@
 // batch.hip -- many independent simulations of uneven sizes advanced together.
 //
-// Each case is a full problem statement (lattice, EOS, T/Tc, kappa, tau, precision, grid).
+// Each case is a full problem statement (lattice, EOS, T/Tc, force model, tau, precision, grid).
 // A step of a case has two phases:
 //   phase 1: pull-gather every node -> rho, signed psi, g = rho u^3 into the case's fields;
 //   phase 2: two-ring Korteweg force from the fields, correction, product-form equilibria
@@ -95,15 +95,15 @@ __device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> 
     static_for<1, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
-        constexpr C w3 = C(3.0 * weight<D>(i));
+        constexpr int cls = cx * cx + cy * cy + cz * cz - 1;   // weight class of c_i
         const int n1 = nb.at(cx, cy, cz);
         const int x2 = wrapi(x + 2 * cx, g.nx), y2 = wrapi(y + 2 * cy, g.ny);
         const int z2 = D == 3 ? wrapi(z + 2 * cz, g.nz) : 0;
         const int n2 = x2 + g.nx * (y2 + g.ny * z2);
         const C p1 = fabs(fpsi[n1]), p2 = fabs(fpsi[n2]);
         const C r1 = frho[n1], r2 = frho[n2];
-        const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
-        const C tc = w3 * (C(2) * r1 - r2);
+        const C tp = p.gw[cls][0] * p1 + p.gw[cls][1] * p2;   // 3w (G1 psi1 + G2 psi2)
+        const C tc = p.gw[cls][2] * r1 + p.gw[cls][3] * r2;   // 3w (G3 rho1 + G4 rho2)
         static_for<0, D>([&](auto A_) {
             constexpr int a = decltype(A_)::value;
             constexpr int ca = Lat<D>::c(i, a);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> 
     });
     C Sf[3] = {C(0), C(0), C(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+    for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + rho * Fc[a]);
     C h[Q];
     if (mask)
         gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
@@ -306,6 +306,11 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
         if (!validate_params(&cases[c], &why)) return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": " + why);
         if (cases[c].link_q)
             return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": link_q (interpolated bounce-back) is not supported by the batch");
+        // the batch kernels index a case's fields in 32-bit ints: field a of node n at a N + n
+        // (a < D) and the block loop's n + stride < 2 N + 256
+        const int D = cases[c].lattice == LBM_D3Q27 ? 3 : 2;
+        if ((double)(D + 1) * cases[c].nx * cases[c].ny * cases[c].nz + 1024.0 >= 2147483648.0)
+            return bfail(nullptr, LBM_E_INVAL, "case " + std::to_string(c) + ": too large for the batch ((D + 1) N must stay below 2^31)");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch;
     if (!b) return bfail(nullptr, LBM_E_NOMEM, "host allocation failed");

@@ -508,10 +508,11 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 constexpr int i = decltype(I)::value;
                 constexpr int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
                 constexpr int o1 = cy * HX + cx;
-                constexpr C w3 = C(3.0 * weight<3>(i));
+                constexpr int cls = cx * cx + cy * cy + cz * cz - 1;   // weight class of c_i
                 const int r1 = base[2 + cz] + e_int + o1, r2 = base[2 + 2 * cz] + e_int + 2 * o1;
-                const C tp = w3 * (C(4.0 / 3.0) * fabs(s_psi[r1]) - C(1.0 / 6.0) * fabs(s_psi[r2]));
-                const C tc = w3 * (C(2) * s_rho[r1] - s_rho[r2]);
+                // 3w (G1 psi1 + G2 psi2) and 3w (G3 rho1 + G4 rho2)
+                const C tp = p.gw[cls][0] * fabs(s_psi[r1]) + p.gw[cls][1] * fabs(s_psi[r2]);
+                const C tc = p.gw[cls][2] * s_rho[r1] + p.gw[cls][3] * s_rho[r2];
                 static_for<0, 3>([&](auto A_) {
                     constexpr int a = decltype(A_)::value;
                     constexpr int ca = Lat<3>::c(i, a);
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 });
             });
 #pragma unroll
-            for (int a = 0; a < 3; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);
+            for (int a = 0; a < 3; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + rho * Fc[a]);
         }
         if (halo) {
             C mh[4];

@@ -22,7 +22,10 @@ struct Geom {
 template <class C> struct Params {
     C rho_ref;      // deviation-storage reference density (0 for plain FP64 storage)
     C rho_w;        // virtual wall density
-    C kappa;        // capillary coefficient
+    C G[4];         // stencil coefficients: G1, G2 (pseudo-potential rings), G3, G4 (capillary
+                    // rings, kappa~ included)
+    C gw[3][4];     // 3 w G_k for the weight class |c|^2 - 1 of a direction: the factors of
+                    // the ring terms, so that a direction costs a multiply and an add
     C omega_l;      // 1/tau_liquid
     C nu_l, nu_v;   // kinematic viscosities of the bulk phases (variable-viscosity mode)
     C rho_l, rho_v; // bulk densities of the viscosity interpolation

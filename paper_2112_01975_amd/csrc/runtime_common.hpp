@@ -80,6 +80,12 @@ inline bool validate_params(const lbm_params *p, std::string *why) {
         return false;
     }
     if (!(p->kappa >= 0) || !isfinite(p->kappa)) { *why = "kappa must be finite and >= 0"; return false; }
+    if (p->force_model < LBM_FORCE_KORTEWEG || p->force_model > LBM_FORCE_GENERAL) {
+        *why = "unknown force model";
+        return false;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(p->force_g[k])) { *why = "force_g must be finite"; return false; }
     if (!(p->tau_liquid > 0.5) || !isfinite(p->tau_liquid)) { *why = "tau_liquid must be > 1/2"; return false; }
     if (p->tau_vapour > 0) {
         if (!(p->tau_vapour > 0.5)) { *why = "tau_vapour must be > 1/2 (or <= 0 for constant tau)"; return false; }
@@ -106,11 +112,34 @@ inline bool validate_params(const lbm_params *p, std::string *why) {
     return true;
 }
 
+// Stencil coefficients (G1, G2, G3, G4) of the force model (Sec. 2.3.4): eq Kforce_final's
+// (4/3, -1/6) from eqs PPcond1/2 and capillary pair (2, -1) kappa~; eq SCforce's single ring
+// (1, 0) without capillary pair; eq DRforce's G2 = (1 - G1)/2 (eq PPcond1 only); or as given.
+inline void force_coefficients(const lbm_params *p, double G[4]) {
+    switch (p->force_model) {
+    case LBM_FORCE_SHAN_CHEN: G[0] = 1.0; G[1] = 0.0; G[2] = 0.0; G[3] = 0.0; break;
+    case LBM_FORCE_DUAL_RANGE:
+        G[0] = p->force_g[0]; G[1] = 0.5 * (1.0 - p->force_g[0]); G[2] = 0.0; G[3] = 0.0;
+        break;
+    case LBM_FORCE_GENERAL: for (int k = 0; k < 4; ++k) G[k] = p->force_g[k]; break;
+    default: G[0] = 4.0 / 3.0; G[1] = -1.0 / 6.0; G[2] = 2.0 * p->kappa; G[3] = -p->kappa; break;
+    }
+}
+
 template <class C> inline void fill_params(const lbm_params *p, Params<C> *q) {
     HostEos e(p->eos, p->a, p->b, p->R, p->acentric, p->T_reduced);
     q->rho_ref = C(p->rho_ref);
     q->rho_w = C(p->rho_wall);
-    q->kappa = C(p->kappa);
+    double G[4];
+    force_coefficients(p, G);
+    // 3 w of a direction by |c|^2: D3Q27 faces 2/9, edges 1/18, corners 1/72; D2Q9 axes 1/3,
+    // diagonals 1/12 (the product-form weights times 1/cs^2)
+    const bool d3 = p->lattice == LBM_D3Q27;
+    const double w3[3] = {d3 ? 2.0 / 9.0 : 1.0 / 3.0, d3 ? 1.0 / 18.0 : 1.0 / 12.0, d3 ? 1.0 / 72.0 : 0.0};
+    for (int k = 0; k < 4; ++k) {
+        q->G[k] = C(G[k]);
+        for (int m = 0; m < 3; ++m) q->gw[m][k] = C(w3[m] * G[k]);
+    }
     q->omega_l = C(1.0 / p->tau_liquid);
     q->var_visc = p->tau_vapour > 0 ? 1 : 0;
     q->nu_l = C((p->tau_liquid - 0.5) / 3.0);

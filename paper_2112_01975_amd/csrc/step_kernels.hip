@@ -11,7 +11,7 @@
 //   per-workgroup partial sums of mass and momentum for the watchdog.
 // Pass 2 (collide): stages rho and the signed pseudo-potential of a 64x4xZB tile
 //   plus a two-node halo in LDS, evaluates the two-ring Korteweg force
-//   (eq Kforce_final), the diagonal correction Phi (eq correction), the product-form
+//   (eq Kforce_final, or the stencil coefficients of another force model), the diagonal correction Phi (eq correction), the product-form
 //   equilibrium and extended equilibrium (eqs LBMeq, LBMstar) in cancellation-free
 //   deviation form, and the LBGK update (eq LBGK).
 #include <hip/hip_runtime.h>
@@ -181,10 +181,12 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             const C rho = s_rho[lc0], sp = s_psi[lc0];
             const C psi = fabs(sp), sg = sp > C(0) ? C(1) : C(-1);
             for (int k = 0; k < NC; ++k) {
-                const C PA = -sg * C(8.0 / 6.0) * psi * ringA[k];
-                const C PB = sg * C(1.0 / 6.0) * (psi * ringB[k] + across[k]);
-                const C PC = -p.kappa * rho * cap1[k];
-                const C PD = C(0.5) * p.kappa * (rho * cap2[k] + capx[k]);
+                // Appendix E's parts for the stencil pairs (G1, G2), (G3, G4): each part is
+                // linear in its coefficient (printed for 4/3, -1/6, 2 kappa, -kappa)
+                const C PA = -sg * p.G[0] * psi * ringA[k];
+                const C PB = -sg * p.G[1] * (psi * ringB[k] + across[k]);
+                const C PC = C(-0.5) * p.G[2] * rho * cap1[k];
+                const C PD = C(-0.5) * p.G[3] * (rho * cap2[k] + capx[k]);
                 // FP32 deviation storage: the reference part w_i rho_ref adds rho_ref/3 on the diagonal
                 const C kin = flux[k] + (k < D ? p.rho_ref * C(1.0 / 3.0) : C(0));
                 out_U[(long long)k * g.N + n] = double(kin) - (double(PA) + double(PB) + double(PC) + double(PD));
@@ -198,11 +200,11 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
             constexpr int i = decltype(I)::value;
             constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
             constexpr int off = (cz * T::LY + cy) * T::LX + cx;
-            constexpr C w3 = C(3.0 * weight<D>(i));
+            constexpr int cls = cx * cx + cy * cy + cz * cz - 1;   // weight class of c_i
             const C p1 = fabs(s_psi[lc + off]), p2 = fabs(s_psi[lc + 2 * off]);
             const C r1 = s_rho[lc + off], r2 = s_rho[lc + 2 * off];
-            const C tp = w3 * (C(4.0 / 3.0) * p1 - C(1.0 / 6.0) * p2);
-            const C tc = w3 * (C(2) * r1 - r2);
+            const C tp = p.gw[cls][0] * p1 + p.gw[cls][1] * p2;   // 3w (G1 psi1 + G2 psi2)
+            const C tc = p.gw[cls][2] * r1 + p.gw[cls][3] * r2;   // 3w (G3 rho1 + G4 rho2)
             static_for<0, D>([&](auto A_) {
                 constexpr int a = decltype(A_)::value;
                 constexpr int ca = Lat<D>::c(i, a);
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         });
         C Sf[3] = {C(0), C(0), C(0)};
 #pragma unroll
-        for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + p.kappa * rho * Fc[a]);   // S = -F + rho g
+        for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + rho * Fc[a]);   // S = -F + rho g
 
         Nbr<D> nb(g, x, y, z);
         C h[Lat<D>::Q];

@@ -20,6 +20,7 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_DOMAIN, LBM_E_DIVERGED, LBM_E
 LBM_D2Q9, LBM_D3Q27 = 0, 1
 LBM_EOS_VDW, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_CS, LBM_EOS_IDEAL, LBM_EOS_SC1, LBM_EOS_SC2 = 0, 1, 2, 3, 4, 5, 6
 LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_FORCE_KORTEWEG, LBM_FORCE_SHAN_CHEN, LBM_FORCE_DUAL_RANGE, LBM_FORCE_GENERAL = 0, 1, 2, 3
 
 EXPORTED = [
     "lbm_create", "lbm_init_fields", "lbm_step", "lbm_moments", "lbm_destroy", "lbm_last_error",
@@ -46,6 +47,7 @@ class lbm_params(C.Structure):
         ("rho_liquid", C.c_double), ("rho_vapour", C.c_double), ("rho_wall", C.c_double),
         ("mask", C.c_void_p), ("precision", C.c_int), ("rho_ref", C.c_double), ("check_every", C.c_int),
         ("accel", C.c_double * 3), ("rho_wall_field", C.c_void_p), ("link_q", C.c_void_p),
+        ("force_model", C.c_int), ("force_g", C.c_double * 4),
     ]
 
 
@@ -136,6 +138,8 @@ class Params:
     accel: tuple = (0.0, 0.0, 0.0)
     rho_wall_field: np.ndarray | None = None
     link_q: np.ndarray | None = None       # [Q][N] wall fractions in lbm_velocities order
+    force_model: int = LBM_FORCE_KORTEWEG
+    force_g: tuple = (0.0, 0.0, 0.0, 0.0)
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -155,7 +159,8 @@ class Params:
                           self.acentric, self.T_reduced, self.kappa, self.tau_liquid, self.tau_vapour,
                           self.rho_liquid, self.rho_vapour, self.rho_wall, _ptr(m), self.precision,
                           self.rho_ref, self.check_every, (C.c_double * 3)(*[float(g) for g in self.accel]),
-                          _ptr(wf), _ptr(lq))
+                          _ptr(wf), _ptr(lq), int(self.force_model),
+                          (C.c_double * 4)(*[float(g) for g in self.force_g]))
 
 
 # ----------------------------------------------------------------- C-named wrappers

@@ -35,6 +35,8 @@ class Case:
     accel: tuple = (0.0, 0.0, 0.0)
     rho_wall_field: np.ndarray | None = None
     link_q: np.ndarray | None = None    # [3,3(,3),N] wall fraction of the link n -> n + c, indexed by c + 1
+    force_model: int = 0                # stencil coefficients of the force (Sec. 2.3.4), same codes both sides
+    force_g: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @property
     def N(self):
@@ -50,7 +52,8 @@ class Case:
         rv, rl = self.coexistence() if self.eos != T.IDEAL else (1.0, 1.0)
         return O.Config(self.lattice, self.nx, self.ny, self.nz, self.eos, self.a, self.b, 1.0, self.acentric,
                         self.T_reduced, self.kappa, self.tau, self.tau_vapour, rl, rv, self.rho_wall,
-                        accel=self.accel, rho_wall_field=self.rho_wall_field, link_q=self.link_q)
+                        accel=self.accel, rho_wall_field=self.rho_wall_field, link_q=self.link_q,
+                        force_model=self.force_model, force_g=self.force_g)
 
     def params(self, precision=0, rho_ref=0.0, check_every=0):
         import paper_2112_01975_amd as P
@@ -58,7 +61,8 @@ class Case:
         return P.Params(P.LBM_D3Q27 if self.lattice == 3 else P.LBM_D2Q9, self.nx, self.ny, self.nz,
                         EOS_OF[self.eos], self.a, self.b, 1.0, self.acentric, self.T_reduced, self.kappa,
                         self.tau, self.tau_vapour, rl, rv, self.rho_wall, self.mask, precision, rho_ref,
-                        check_every, self.accel, self.rho_wall_field, self.library_link_q())
+                        check_every, self.accel, self.rho_wall_field, self.library_link_q(),
+                        force_model=self.force_model, force_g=self.force_g)
 
     def library_link_q(self):
         """link_q as the library takes it: [Q][N] in lbm_velocities order."""
@@ -143,7 +147,8 @@ def oracle_one_step_at_nodes(case: Case, pops_bytes, precision, rho_ref, nodes, 
         cube = Case(D, m, m, m if D == 3 else 1, case.eos, case.a, case.b, case.acentric, case.T_reduced,
                     case.kappa, case.tau, case.tau_vapour, case.rho_wall,
                     None if mask is None else mask[idx].copy(), case.accel,
-                    None if case.rho_wall_field is None else case.rho_wall_field[idx].copy())
+                    None if case.rho_wall_field is None else case.rho_wall_field[idx].copy(),
+                    force_model=case.force_model, force_g=case.force_g)
         cfg = cube.oracle_config()
         if case.tau_vapour > 0:
             rv, rl = case.coexistence()

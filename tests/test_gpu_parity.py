@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import lbm_inputs as L
+from oracle import oracle as O
 from oracle import thermo as T
 from tests.gpu_cases import Case, drop_case_inputs, max_rel, run_gpu, run_oracle, slab_case_inputs
 
@@ -53,6 +54,36 @@ def test_every_eos_d2q9_fp64(eos, a, om, tr, kappa):
     case = Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr, kappa=kappa)
     rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 7)
     _cmp64(case, rho0, u0, 300)
+
+
+# force models (Sec. 2.3.4): the single-ring Shan-Chen force (eq SCforce), the dual-range force
+# (eq DRforce) and general stencil coefficients, with Shan-Chen and cubic EOS
+FORCE_CASES_2D = [(O.FORCE_SHAN_CHEN, (0.0, 0.0, 0.0, 0.0), T.SC1, 0.0, 0.0, 0.9),
+                  (O.FORCE_DUAL_RANGE, (1.1, 0.0, 0.0, 0.0), T.VDW, 0.02, 0.0, 0.8),
+                  (O.FORCE_GENERAL, (1.2, -0.1, 0.04, -0.02), T.VDW, 0.02, 0.0, 0.8)]
+
+
+@pytest.mark.parametrize("model,g,eos,a,om,tr", FORCE_CASES_2D)
+def test_force_models_d2q9_fp64(model, g, eos, a, om, tr):
+    case = Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr, kappa=0.0, force_model=model, force_g=g)
+    rho0, u0 = slab_case_inputs(case, 4.0, 1e-4, 7)
+    _cmp64(case, rho0, u0, 300)
+
+
+@pytest.mark.parametrize("model,g,eos,a,om,tr", [(O.FORCE_SHAN_CHEN, (0.0, 0.0, 0.0, 0.0), T.SC2, 0.0, 0.0, 0.9),
+                                                 (O.FORCE_DUAL_RANGE, (1.2, 0.0, 0.0, 0.0), T.PR, 0.005046, 0.344,
+                                                  0.6)])
+def test_force_models_d3q27_fused_fp64_and_fp32(model, g, eos, a, om, tr):
+    # through the single-pass kernels (x ragged over two tiles): FP64 element by element, and
+    # FP32 deviation storage on the densities
+    case = Case(3, 70, 24, 20, eos=eos, a=a, acentric=om, T_reduced=tr, kappa=0.0, force_model=model, force_g=g)
+    rho0, u0 = drop_case_inputs(case, 6.0, 4.0, 1e-5, 1004, centre=(35.0, 12.0, 10.0))
+    _cmp64(case, rho0, u0, 100)
+    if eos == T.SC2:
+        rv, _ = case.coexistence()
+        r32, _, _ = run_gpu(case, rho0, u0, 100, precision=1, rho_ref=rv)
+        r64, _, _ = run_oracle(case, rho0, u0, 100)
+        assert max_rel(r32, r64) < 1e-4
 
 
 def test_ideal_gas_shear_wave_fp64():
@@ -355,10 +386,15 @@ def test_batched_sweep_matches_single_runs_and_oracle(stepped, monkeypatch):
                                  rho_ref=rv if not sc.fp64 else 0.0)
             tol = 1e-12 if sc.fp64 else 2e-5
             assert max_rel(rb, rs) < tol, (i, max_rel(rb, rs))
+            ro, Uo, to = run_oracle(c, rho0, None, 301)
             if sc.fp64:
-                ro, Uo, to = run_oracle(c, rho0, None, 301)
                 assert max_rel(rb, ro) < FP64_RHO_TOL
                 assert np.abs(Ub - Uo).max() < FP64_U_TOL
+            else:
+                # FP32 deviation storage against the FP64 oracle, node by node: stated bound
+                # 1e-4 in density (the FP32 bound of the coexistence densities) and 1e-5 in U
+                assert max_rel(rb, ro) < 1e-4, (i, max_rel(rb, ro))
+                assert np.abs(Ub - Uo).max() < 1e-5, (i, np.abs(Ub - Uo).max())
     finally:
         P.lbm_batch_destroy(b)
 
@@ -383,6 +419,31 @@ def test_batched_mixed_lattices_and_masks(stepped, monkeypatch):
             ro, Uo, _ = run_oracle(c, r0, None, 60)
             assert max_rel(rb, ro) < FP64_RHO_TOL
             assert np.abs(Ub - Uo).max() < FP64_U_TOL
+    finally:
+        P.lbm_batch_destroy(b)
+
+
+@pytest.mark.parametrize("stepped", ["1", "0"])
+def test_batched_force_models(stepped, monkeypatch):
+    # cases with different force models side by side in one batch: each against the oracle
+    # (FP64) and against its single run (bit for bit)
+    monkeypatch.setenv("LBM2P_BATCH_STEPPED", stepped)
+    import paper_2112_01975_amd as P
+    cases = [Case(2, 48, 20, eos=eos, a=a, acentric=om, T_reduced=tr, kappa=0.0, force_model=model, force_g=g)
+             for model, g, eos, a, om, tr in FORCE_CASES_2D]
+    cases.append(Case(2, 48, 20, a=0.02, T_reduced=0.8))          # the default Korteweg force
+    inits = [slab_case_inputs(c, 4.0, 1e-4, 7)[0] for c in cases]
+    b = P.lbm_batch_create([c.params(0) for c in cases])
+    try:
+        for i, r0 in enumerate(inits):
+            P.lbm_batch_init_fields(b, i, r0)
+        P.lbm_batch_step(b, 120)
+        for i, (c, r0) in enumerate(zip(cases, inits)):
+            rb, Ub, _ = P.lbm_batch_moments(b, i, c.N, 2)
+            ro, Uo, _ = run_oracle(c, r0, None, 120)
+            assert max_rel(rb, ro) < FP64_RHO_TOL and np.abs(Ub - Uo).max() < FP64_U_TOL, i
+            rs, Us, _ = run_gpu(c, r0, None, 120)
+            assert max_rel(rb, rs) < 1e-12, i
     finally:
         P.lbm_batch_destroy(b)
 

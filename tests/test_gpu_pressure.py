@@ -48,6 +48,21 @@ def test_pressure_tensor_parity_random_walls(D, dims, interp):
     assert np.abs(Pf - Po).max() < 1e-6 * rl / 3
 
 
+@pytest.mark.parametrize("D,model,g", [(2, O.FORCE_DUAL_RANGE, (1.1, 0.0, 0.0, 0.0)),
+                                       (3, O.FORCE_GENERAL, (1.2, -0.1, 0.04, -0.02))])
+def test_pressure_tensor_parity_other_force_models(D, model, g):
+    # Appendix E's parts scaled by the stencil coefficients of the force model
+    nx, ny, nz = (37, 29, 1) if D == 2 else (21, 14, 11)
+    N = nx * ny * nz
+    fl = T.Fluid(T.VDW, 0.02, 2 / 21, 0.8)
+    rv, rl, _ = T.coexistence(fl)
+    case = Case(D, nx, ny, nz, a=0.02, T_reduced=0.8, rho_wall=0.5 * (rv + rl), mask=L.random_mask(nx, ny, nz, 0.1, 8),
+                force_model=model, force_g=g)
+    rho0, u0 = L.random_state(N, D, rv, rl, 0.02, 9)
+    Pg, Po = _tensors(case, rho0, u0, 20)
+    assert np.abs(Pg - Po).max() < 1e-10 * np.abs(Po).max()
+
+
 def test_pressure_tensor_parity_drop_d3q27_64():
     case = Case(3, 64, 64, 64, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
     rv, rl = case.coexistence()

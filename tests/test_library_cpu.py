@@ -82,6 +82,8 @@ def _wall_rows(rows, q):
     (dict(lattice=1, nx=1400, ny=1400, nz=1400), "larger than 2^31"),
     # 1025 x 1427^2 fits below 2^31 nodes, but not with its rows padded to 1056
     (dict(lattice=1, nx=1025, ny=1427, nz=1427), "with its rows padded"),
+    (dict(force_model=4), "force model"),
+    (dict(force_model=2, force_g=(float("nan"), 0.0, 0.0, 0.0)), "force_g"),
 ])
 def test_create_rejects_bad_parameters_without_gpu(bad, msg):
     import paper_2112_01975_amd as P
@@ -101,6 +103,18 @@ def test_batch_rejects_interpolated_walls_without_gpu():
     with pytest.raises(P.LbmError) as ei:
         P.lbm_batch_create([p])
     assert ei.value.code == P.LBM_E_INVAL and "not supported by the batch" in str(ei.value)
+
+
+@pytest.mark.parametrize("lattice,dims", [(0, (32768, 32768, 1)), (1, (1024, 1024, 600))])
+def test_batch_rejects_cases_past_its_32_bit_field_offsets_without_gpu(lattice, dims):
+    # the batch kernels address a case's fields at a N + n and step blocks by about N in
+    # 32-bit ints: cases with (D + 1) N >= 2^31 are rejected before any device use
+    import paper_2112_01975_amd as P
+    nx, ny, nz = dims
+    small = P.Params(P.LBM_D2Q9, 16, 4, 1)
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_batch_create([small, P.Params(lattice, nx, ny, nz)])
+    assert ei.value.code == P.LBM_E_INVAL and "case 1: too large for the batch" in str(ei.value)
 
 
 def test_velocity_sets_are_the_full_stencils():
