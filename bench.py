@@ -83,12 +83,15 @@ def size_sweep(P, torch, boxes, steps=10, warmup=3):
         out[name] = {"ms_per_step": round(ms[1] / steps, 4), "GLUPS": round(p.N * steps / ms[1] / 1e6, 2),
                      "fused": bool(nl[0] == 0), "finite": bool(np.isfinite(tot).all())}
         log(f"[bench] size {name}: {out[name]}")
-    out["copy_probe_GBs"] = round(copy_probe(torch)["GBs"], 1)
+    out["copy_probe_GBs"] = round(copy_probe(P, torch)["GBs"], 1)
     return out
 
 
-def time_leg(P, torch, n, precision, steps, warmup):
-    p, rho0, meta = workload(P, n, precision)
+def time_leg(P, torch, n, precision, steps, warmup, check_every=1000):
+    """Time `steps` steps of lbm_step with the FP64 watchdog every `check_every` steps (and at
+    the end of the call); then the per-launch kernel time from HIP events, and the cost of one
+    watchdog check: K calls of one step (each ending in a check) against one call of K steps."""
+    p, rho0, meta = workload(P, n, precision, check_every)
     sim = P.Simulation(p)
     sim.init(rho0)
     _, _, tot0 = sim.moments(want_fields=False)
@@ -102,25 +105,36 @@ def time_leg(P, torch, n, precision, steps, warmup):
     kt = max(5, min(steps, 20))
     ms, nl = P.lbm_step_timed(sim.ctx, kt)   # HIP events around every launch
     kern = {"moment_pass": ms[0] / nl[0] if nl[0] else 0.0, "step_kernel": ms[1] / nl[1]}
+    K = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.lbm_step(sim.ctx, K)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(K):
+        P.lbm_step(sim.ctx, 1)
+    torch.cuda.synchronize()
+    t_each = time.perf_counter() - t0
+    check_ms = max(0.0, (t_each - t_one) / (K - 1)) * 1e3
     return sim, {"mlups": n ** 3 * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps, "kernel_ms": kern,
-                 "fused": nl[0] == 0, "steps_total": warmup + steps + kt, "mass0": tot0[0]}, meta
+                 "fused": nl[0] == 0, "steps_total": warmup + steps + kt + 2 * K, "mass0": tot0[0],
+                 "check_ms": check_ms, "check_every": check_every}, meta
 
 
-def copy_probe(torch, nbytes=1 << 30, reps=5):
-    """Plain device copy of known size: attainable bandwidth (and the counter scale in profiles)."""
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+def copy_probe(P, torch, nbytes=1 << 32, reps=5):
+    """Attainable copy bandwidth: the library's hand-written streaming copy (16-byte accesses,
+    non-temporal loads and stores, the fastest of a few launch shapes) over two 4 GiB device
+    buffers; also the counter scale of the traffic profiles."""
+    x = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    y.copy_(x)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        y.copy_(x)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 1e3 / reps
+    gbs, ms, shape = P.lbm_copy_probe(y.data_ptr(), x.data_ptr(), nbytes, reps,
+                                      torch.cuda.current_stream().cuda_stream)
     del x, y
-    return {"bytes_per_copy": 2 * nbytes, "GBs": 2 * nbytes / t / 1e9}
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "GBs": gbs, "ms": ms,
+            "shape": f"{shape // 100000} x 16 B in flight per lane, {shape % 100000} workgroups"}
 
 
 def traffic_from_profile():
@@ -200,7 +214,7 @@ def other_workloads(P, torch):
       tau 0.8): the whole lattice fits in the MALL, so only MLUPS are meaningful;
     - D3Q27 512 x 256 x 256 drop impact on a textured wall (floor plus 8 x 8 pillars of
       height 16 every 16 nodes; Peng-Robinson T/Tc = 0.6, a for W = 5, kappa 0.02;
-      nu_vapour = 15 nu_liquid with tau_liquid = 0.55; wall density = vapour density;
+      nu_vapour = 15 nu_liquid with tau_liquid = 0.55 (and 0.51, FP32); wall density = vapour density;
       drop R = 40 at (256, 128, 77) moving at -0.05 along z): MLUPS over all nodes and
       MFLUPS over fluid nodes."""
     import lbm_inputs as L
@@ -223,9 +237,10 @@ def other_workloads(P, torch):
     mask = L.pillar_mask(nx, ny, nz, 8, 8, 16)
     fluid = int((mask == 0).sum())
     d3 = {}
-    for prec, name in ((P.LBM_FP32_DEV, "fp32"), (P.LBM_FP64, "fp64")):
-        p = P.Params(P.LBM_D3Q27, nx, ny, nz, P.LBM_EOS_PR, a3, B21, 1.0, 0.344, 0.6, 0.02, 0.55,
-                     tau_vapour=0.5 + 15 * 0.05, mask=mask, precision=prec, check_every=-1)
+    for prec, name, tau in ((P.LBM_FP32_DEV, "fp32", 0.55), (P.LBM_FP64, "fp64", 0.55),
+                            (P.LBM_FP32_DEV, "fp32_tau_liquid_0.51", 0.51)):
+        p = P.Params(P.LBM_D3Q27, nx, ny, nz, P.LBM_EOS_PR, a3, B21, 1.0, 0.344, 0.6, 0.02, tau,
+                     tau_vapour=0.5 + 15 * (tau - 0.5), mask=mask, precision=prec, check_every=-1)
         rv, rl, _, _ = P.lbm_coexistence(p)
         p.rho_liquid, p.rho_vapour, p.rho_wall = rl, rv, rv
         p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
@@ -302,12 +317,12 @@ def pressure_tensor_leg(P, torch, n, reps=3):
     return out
 
 
-def cpu_baseline(budget_s=12.0):
-    """The FP64 oracle on a bounded sample of the same workload (48^3, same physics)."""
+def cpu_baseline(n=256, budget_s=15.0):
+    """The FP64 oracle on the headline workload itself (n^3 drop, same physics): a bounded
+    sample of whole oracle steps after one untimed step, timed on the host's cores."""
     from oracle import oracle as O
     from oracle import thermo as T
     import lbm_inputs as L
-    n = 48
     fl0 = T.Fluid(T.PR, 2.0 / 49.0, B21, 0.6, 1.0, 0.344)
     a = fl0.a * 0.02 / T.kappa_for_width(fl0, 5.0)
     fl = T.Fluid(T.PR, a, B21, 0.6, 1.0, 0.344)
@@ -317,12 +332,13 @@ def cpu_baseline(budget_s=12.0):
     orc.step(1)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        orc.step(2)
-        steps += 2
+        orc.step(1)
+        steps += 1
     dt = time.perf_counter() - t0
+    orc.close()
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"D3Q27 {n}^3 drop (same EOS, T/Tc, kappa, tau; radius scaled to 9.4), {steps} FP64 "
-                      f"steps in {dt:.1f} s",
+            "sample": f"the D3Q27 {n}^3 drop workload itself (same EOS, T/Tc, kappa, tau, radius "
+                      f"{50.0 * n / 256:g}), {steps} FP64 oracle steps in {dt:.1f} s after one untimed step",
             "host": host_cpu()}
 
 
@@ -351,6 +367,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--error-steps", type=int, default=5000,
+                    help="steps after which the FP32 state is compared with the FP64 state (untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
@@ -391,18 +409,29 @@ def main():
     N = n ** 3
     log(f"[bench] FP32 deviation-storage leg {n}^3 warmup={args.warmup} steps={args.steps}")
     sim32, r32, (rv, rl, a) = time_leg(P, torch, n, P.LBM_FP32_DEV, args.steps, args.warmup)
-    log(f"[bench] FP32 {r32['mlups']:.0f} MLUPS, kernels {r32['kernel_ms']}")
-    probe = copy_probe(torch)
-    log(f"[bench] copy probe {probe['GBs']:.0f} GB/s")
+    log(f"[bench] FP32 {r32['mlups']:.0f} MLUPS, kernels {r32['kernel_ms']}, check {r32['check_ms']:.3f} ms")
+    probe = copy_probe(P, torch)
+    log(f"[bench] copy probe {probe['GBs']:.0f} GB/s ({probe['shape']})")
     fp64 = None
     dens = None
-    rho32, _, t32 = sim32.moments()
+    _, _, t32_timed = sim32.moments(want_fields=False)
     if not args.no_fp64:
         log("[bench] FP64 leg")
         sim64, r64, _ = time_leg(P, torch, n, P.LBM_FP64, args.steps, args.warmup)
-        log(f"[bench] FP64 {r64['mlups']:.0f} MLUPS, kernels {r64['kernel_ms']}")
+        log(f"[bench] FP64 {r64['mlups']:.0f} MLUPS, kernels {r64['kernel_ms']}, check {r64['check_ms']:.3f} ms")
+        _, _, t64_timed = sim64.moments(want_fields=False)
+        # the precision comparison at the workload's full length: both states continued to
+        # `error_steps` steps in all (untimed)
+        total = max(args.error_steps, r32["steps_total"])
+        log(f"[bench] FP32 and FP64 continued to {total} steps")
+        sim32.step(total - r32["steps_total"])
+        sim64.step(total - r64["steps_total"])
+        rho32, _, t32 = sim32.moments()
         rho64, _, t64 = sim64.moments()
-        dens = {"after_steps": r32["steps_total"], "rho_ref": "rho_vapour", **density_error(rho32, rho64, n)}
+        dens = {"after_steps": total, "rho_ref": "rho_vapour", **density_error(rho32, rho64, n),
+                "mass_rel_drift_fp32": abs(t32[0] / r32["mass0"] - 1),
+                "mass_rel_drift_fp64": abs(t64[0] / r64["mass0"] - 1)}
+        del rho32
         # the other references the deviation storage could take (liquid density, mean of the two)
         alt = {}
         for name, ref in (("rho_liquid", rl), ("mean", 0.5 * (rl + rv))):
@@ -411,21 +440,23 @@ def main():
             with P.Simulation(p_alt) as s_alt:
                 s_alt.init(rho0_alt)
                 del rho0_alt
-                s_alt.step(r32["steps_total"])
+                s_alt.step(total)
                 rho_alt, _, _ = s_alt.moments()
             alt[name] = density_error(rho_alt, rho64, n)
             del rho_alt
         dens["other_rho_ref"] = alt
+        del rho64
         log(f"[bench] FP32 density error {dens}")
         t_k = r64["kernel_ms"]["step_kernel"] * 1e-3
         b64 = (2 * 27 + 4) * 8 if not r64["fused"] else 2 * 27 * 8
         fp64 = {"value": r64["mlups"], "unit": "MLUPS", "ms_per_step": r64["ms_per_step"],
                 "kernel": "collide-stream pass (two-pass step)" if not r64["fused"] else "fused step",
-                "kernel_ms": r64["kernel_ms"],
+                "kernel_ms": r64["kernel_ms"], "watchdog_check_ms": r64["check_ms"],
                 "roofline": {"bound": "hbm", "achieved": N * b64 / t_k / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": N * b64 / t_k / 1e9 / HBM_PEAK_GBS, "bytes_per_lup": b64},
+                             "frac": N * b64 / t_k / 1e9 / HBM_PEAK_GBS, "bytes_per_lup": b64,
+                             "frac_of_attainable_copy": N * b64 / t_k / 1e9 / probe["GBs"]},
                 "useful_frac_step": r64["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9),
-                "mass_rel_drift": abs(t64[0] / r64["mass0"] - 1)}
+                "mass_rel_drift_timed": abs(t64_timed[0] / r64["mass0"] - 1)}
         sim64.close()
     sim32.close()
     t_k = r32["kernel_ms"]["step_kernel"] * 1e-3
@@ -453,7 +484,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"D3Q27 {n}^3 periodic static drop R={50 * n / 256:g} at rest, Peng-Robinson "
                                f"omega'=0.344 T/Tc=0.6 (rho_l/rho_v={rl / rv:.0f}), kappa=0.02, a={a:.6g}, "
-                               f"b=2/21, W=5, tau=0.8, FP32 deviation storage (rho_ref=rho_v)",
+                               f"b=2/21, W=5, tau=0.8, FP32 deviation storage (rho_ref=rho_v), FP64 watchdog "
+                               f"every {r32['check_every']} steps and at the end of each lbm_step call",
                    "nodes": N, "lattice": "D3Q27", "precision": "fp32-deviation", "kernel": "fused z-march"
                    if r32["fused"] else "two-pass"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -467,7 +499,11 @@ def main():
                                       if traffic else None)},
         "useful_frac_step": r32["mlups"] * 1e6 * bytes_lup / (HBM_PEAK_GBS * 1e9),
         "attainable_copy_GBs": probe["GBs"],
-        "mass_rel_drift_fp32": abs(t32[0] / r32["mass0"] - 1),
+        "attainable_copy": probe,
+        "frac_of_attainable_copy": achieved / probe["GBs"],
+        "watchdog": {"check_every": r32["check_every"], "check_ms": r32["check_ms"],
+                     "check_frac_of_step": r32["check_ms"] / r32["ms_per_step"]},
+        "mass_rel_drift_fp32": abs(t32_timed[0] / r32["mass0"] - 1),
         "density_error_fp32_vs_fp64": dens,
         "fp64": fp64,
         "batch_sweep": batch,

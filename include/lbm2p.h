@@ -86,7 +86,14 @@ typedef struct {
     double rho_ref;         /* reference density of the FP32 deviation storage */
     int check_every;        /* watchdog period in steps inside lbm_step: > 0 every
                                check_every steps and at the end, 0 at the end only,
-                               < 0 never */
+                               < 0 never. A check reduces FP64 mass and momentum totals
+                               and the count of densities outside the EOS domain. After
+                               a single-pass (D3Q27) FP32 step on a grid without mask it
+                               reduces the totals that step accumulated while pulling its
+                               input state, i.e. the state one step before the check, with
+                               no extra pass over the lattice; otherwise it runs a moment
+                               pass on the current state. lbm_moments always reports the
+                               current state */
     double accel[3];        /* body-force acceleration g (layered Poiseuille flow, Sec. 4.2):
                                the momentum source gains rho g, so U and the equilibria
                                carry it as they carry the Korteweg force; finite; z = 0
@@ -167,6 +174,15 @@ void lbm_destroy(lbm_ctx *c);
  * lbm_batch_create when c is NULL. Never NULL; valid until the next call. */
 const char *lbm_last_error(const lbm_ctx *c);
 
+/* Result of the latest watchdog check (lbm_init_fields, lbm_set_populations, and the checks
+ * of lbm_step selected by check_every): out[0..3] = FP64 totals {sum rho, sum rho u_x,
+ * sum rho u_y, sum rho u_z} over fluid nodes (unshifted u), out[4] = the number of fluid
+ * nodes whose density is outside the EOS domain; *state_step (nullable) = the number of
+ * steps since the last initialisation of the state they describe (one less than the steps
+ * taken when the check reduced the totals the single-pass step accumulates). Host copy of
+ * values already read; LBM_E_STATE before the first check. */
+int lbm_last_check(const lbm_ctx *c, double out[5], int64_t *state_step);
+
 /* Makes the context enqueue its work on hip_stream (a hipStream_t, not owned);
  * NULL restores the context's own stream. */
 int lbm_set_stream(lbm_ctx *c, void *hip_stream);
@@ -194,6 +210,16 @@ int lbm_velocities(int lattice, int *c);
  * ms[2] = everything in the step loop. launches[0..1] = number of launches.
  * A measurement mode for the bench; the state advances exactly as lbm_step. */
 int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]);
+
+/* Attainable HBM bandwidth (measurement aid, not part of the method): copies `bytes`
+ * (a multiple of 16) from src to dst, both device buffers of at least that size owned by
+ * the caller, with a hand-written streaming kernel (16-byte accesses, non-temporal loads
+ * and stores) in a few launch shapes, reps timed launches each, on hip_stream (a
+ * hipStream_t, NULL = the default stream). out[0] = the fastest shape's bandwidth in GB/s
+ * counting bytes read plus written, out[1] = its ms per copy, out[2] = its shape code
+ * (loads in flight per lane x 100000 + workgroups). Synchronous; LBM_E_INVAL for bad
+ * arguments, LBM_E_HIP if a launch or event fails. */
+int lbm_copy_probe(void *dst, const void *src, int64_t bytes, int reps, void *hip_stream, double out[3]);
 
 /* Thermodynamics of the problem statement, host only (Sec. 3.1). out[0] = rho_v,
  * out[1] = rho_l, out[2] = P_sat from the Maxwell equal-area rule

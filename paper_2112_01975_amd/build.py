@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm2p.so")
 BUILD = os.path.join(ROOT, "_build", "lbm2p")
 
-SOURCES = ["step_kernels.hip", "fused_kernels.hip", "runtime.hip", "batch.hip", "thermo_host.cpp"]
+SOURCES = ["step_kernels.hip", "fused_kernels.hip", "runtime.hip", "batch.hip", "probe.hip", "thermo_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -42,7 +42,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -221,7 +221,7 @@ struct lbm_batch {
     int *d_order = nullptr, *d_parity = nullptr;
     int n2 = 0, n3 = 0;              // cases per lattice; d_order lists the D2Q9 cases first
     std::vector<void *> allocs;
-    double *partials = nullptr, *d_tot = nullptr, *io = nullptr;
+    double *partials = nullptr, *d_tot = nullptr, *io = nullptr, *rscratch = nullptr;
     size_t io_elems = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -370,7 +370,8 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
     b->partials = (double *)dalloc((size_t)max_nblk * kPartialSlots * sizeof(double));
     b->d_tot = (double *)dalloc(8 * sizeof(double));
     b->io = (double *)dalloc(b->io_elems * sizeof(double));
-    if (!b->d_cases || !b->d_order || !b->d_parity || !b->partials || !b->d_tot || !b->io) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    b->rscratch = (double *)dalloc((size_t)reduce_scratch_rows(max_nblk) * kPartialSlots * sizeof(double));
+    if (!b->d_cases || !b->d_order || !b->d_parity || !b->partials || !b->d_tot || !b->io || !b->rscratch) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
     // largest cases first: they bound the launch, so they are dispatched first
     std::vector<int> order(ncases);
     for (int c = 0; c < ncases; ++c) order[c] = c;
@@ -528,7 +529,7 @@ int lbm_batch_moments(lbm_batch *b, int icase, double *rho, double *U, double to
     const size_t N = (size_t)cd.g.N;
     // the two-pass moment kernel refreshes rho and g in the case's fields and writes partials
     b->ks[icase].moments(b->stream, A, cd.g, cd.mask, prm, cd.frho, cd.fg, b->partials);
-    launch_reduce(b->stream, b->partials, b->nblk[icase], b->d_tot);
+    launch_reduce(b->stream, b->partials, b->nblk[icase], b->rscratch, b->d_tot);
     double t[5];
     BHIP(b, hipMemcpyAsync(t, b->d_tot, 5 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     if (rho || U) {

@@ -17,6 +17,10 @@ struct FusedGrid {
     int item0, count;      // this launch runs items [item0, item0 + count)
     int per_xcd;           // items per XCD (ceil(count / 8))
     int blocks;            // launched workgroups = 8 * per_xcd
+    double *partials;      // nullable: item i writes the FP64 totals (mass, momentum, domain
+                           // count; kPartialSlots values) of the nodes it collides, as pulled
+                           // from the input state, into row slot0 + i
+    int slot0;
 };
 
 FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze);

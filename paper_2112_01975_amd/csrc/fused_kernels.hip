@@ -10,6 +10,11 @@
 // correction (eq correction) from g, and the populations from a register queue,
 // so every population crosses HBM once in each direction (2 Q s bytes per lattice update plus the chunk's z halo).
 //
+// In FP32 on grids without solid nodes the FP64 mass and momentum totals of the input
+// state ride along: each thread adds the moments of the tile nodes it collides as they are staged, and
+// each work item leaves one row of partial sums (wave shuffles, then LDS) for the watchdog's
+// reduction tree.
+//
 // Software pipeline, one barrier per plane: while plane z is collided, the
 // population registers of plane z are refilled with the pulls of plane z+3 as soon
 // as each collided value is stored, and the halo pulls of plane z+3 are in flight
@@ -353,6 +358,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     // plane z again when it is collided.
     C q0[27], q1[REPULL ? 1 : 27], q2[REPULL ? 1 : 27];
     C m0[4], m1[4], m2[4];
+    // FP64 totals of the tile nodes this thread collides: mass, momentum, and the count of
+    // densities outside the EOS domain. Only the unmasked FP32 kernels keep them: in the
+    // others the nine registers cost spills (the FP64 step 4% of its time), and their checks
+    // run the moment pass.
+    constexpr bool TOT = !MASK && sizeof(C) == 4;
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    int bad = 0;
 
     // byte offsets of planes pz-1, pz, pz+1 (any integer pz)
     auto planes = [&](int pz, unsigned (&zs)[3]) __attribute__((always_inline)) {
@@ -382,7 +394,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
     // rho, s*psi and g_x, g_y of one staged node into ring slot `slot` / g buffer `buf`;
     // returns g_z. h holds the node's pulled populations, m receives (sum h, j); node is
     // its lattice index (for the wall density of a solid node).
-    auto stage = [&](int e, bool solid, unsigned node, const C (&h)[27], C (&m)[4], int slot, int buf)
+    auto stage = [&](int e, bool solid, unsigned node, const C (&h)[27], C (&m)[4], int slot, int buf, bool count)
         __attribute__((always_inline)) {
         C rho, ga[3] = {C(0), C(0), C(0)};
         if (MASK && solid) {
@@ -392,6 +404,13 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             moments_of<3, C>(h, sum, j);
             m[0] = sum; m[1] = j[0]; m[2] = j[1]; m[3] = j[2];
             rho = p.rho_ref + sum;
+            if (TOT && count) {   // a tile node of a plane this item collides
+                tot[0] += double(rho);
+                tot[1] += double(j[0]);
+                tot[2] += double(j[1]);
+                tot[3] += double(j[2]);
+                bad += p.eos.in_domain(rho) ? 0 : 1;
+            }
             const C rinv = rcp(rho);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -431,7 +450,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                     constexpr int q = decltype(Q)::value;
                     s_q[(j * NQ + q) * NT + t] = h[queued(q)];
                 });
-        const C gzn = stage(e_int, solid, (si.v[1][1] + zs[1]) / SB, h, m, slot, buf);
+        const C gzn = stage(e_int, solid, (si.v[1][1] + zs[1]) / SB, h, m, slot, buf, own && j >= 0 && j < tzi);
         if (has_halo) {
             C hh[27], mh[4];
             const uint32_t lh = MM ? links_at(sh, zs) : 0u;
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
                 pull_all<S, C, MM>(Ab, lh, sh, zs, hh);
                 if constexpr (MM) fix(Ab, lh, qlo_at(sh, zs), sh, zs, hh);
             }
-            stage(e_halo, hs, (sh.v[1][1] + zs[1]) / SB, hh, mh, slot, buf);
+            stage(e_halo, hs, (sh.v[1][1] + zs[1]) / SB, hh, mh, slot, buf, false);
         }
         __syncthreads();
         shift_windows(gzn, buf);
@@ -528,7 +547,7 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             if (REPULL && !((lh >> LINK_SELF) & 1u)) pull_all<S, C, MM>(Ab, lh, sh, zs3, hh);
             if constexpr (MM)
                 if (!((lh >> LINK_SELF) & 1u)) fix(Ab, lh, bh, sh, zs3, hh);
-            stage(e_halo, (lh >> LINK_SELF) & 1u, (sh.v[1][1] + zs3[1]) / SB, hh, mh, slot, buf);
+            stage(e_halo, (lh >> LINK_SELF) & 1u, (sh.v[1][1] + zs3[1]) / SB, hh, mh, slot, buf, false);
         }
 
         // refill with plane z+3, which feeds the stencil of z+1; past the chunk the
@@ -594,7 +613,9 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
         C gzn = C(0);
         if constexpr (MM)
             if (need3 && !((l3 >> LINK_SELF) & 1u)) fix(Ab, l3, b3, si, zs3, qa);
-        if (need3) gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, (si.v[1][1] + zs3[1]) / SB, qa, ma, slot, buf);
+        if (need3)
+            gzn = stage(e_int, (l3 >> LINK_SELF) & 1u, (si.v[1][1] + zs3[1]) / SB, qa, ma, slot, buf,
+                        own && k + 3 < tzi);
         if constexpr (LQ)
             if (need3)
                 static_for<0, NQ>([&](auto Q) {
@@ -639,6 +660,26 @@ __global__ __launch_bounds__(FTX * TY) void k_fused3(const S *__restrict__ A, S 
             march(k, q0, m0);
             if (k + 1 < tzi) march(k + 1, q1, m1);
             if (k + 2 < tzi) march(k + 2, q2, m2);
+        }
+    }
+    // one row of FP64 partial sums per work item, in a fixed order: wave64 shuffles, then the
+    // waves' sums from LDS
+    if (TOT && fg.partials) {
+        __shared__ double s_red[NT / 64][kPartialSlots];
+        double v[kPartialSlots] = {tot[0], tot[1], tot[2], tot[3], double(bad)};
+#pragma unroll
+        for (int q = 0; q < kPartialSlots; ++q)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+        if ((t & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < kPartialSlots; ++q) s_red[t >> 6][q] = v[q];
+        __syncthreads();
+        if (t < kPartialSlots) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) sum += s_red[w][t];
+            fg.partials[(long long)(fg.slot0 + item) * kPartialSlots + t] = sum;
         }
     }
 }
@@ -712,6 +753,8 @@ FusedGrid fused_grid(const Geom &g, int tx, int ty, int tz, int zb, int ze) {
     f.count = f.items;
     f.per_xcd = (f.items + NXCD - 1) / NXCD;
     f.blocks = f.per_xcd * NXCD;
+    f.partials = nullptr;
+    f.slot0 = 0;
     return f;
 }
 

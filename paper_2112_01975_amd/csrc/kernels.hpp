@@ -68,7 +68,9 @@ struct KernelSet {
 KernelSet kernel_set(int D, bool fp64, bool masked);
 int moment_block_count(int D, const Geom &g);
 
-// deterministic FP64 tree over nblocks partial rows -> totals[0..4]
-void launch_reduce(hipStream_t s, const double *partials, int nblocks, double *totals);
+// deterministic FP64 tree over n partial rows of kPartialSlots values -> totals[0..4]: levels
+// of 2048 rows per workgroup; scratch holds reduce_scratch_rows(n) rows of intermediate sums
+void launch_reduce(hipStream_t s, const double *partials, int n, double *scratch, double *totals);
+long long reduce_scratch_rows(int n);
 
 }  // namespace lbm

@@ -34,7 +34,17 @@ struct lbm_ctx {
     uint32_t *qlo = nullptr;         // q < 1/2 bits of the wall links for the fused step (link_q only)
     void *wall = nullptr;            // per-node wall densities in compute precision (optional)
     void *lq = nullptr;              // per-link wall fractions in compute precision (optional)
-    double *partials = nullptr, *totals = nullptr;
+    double *partials = nullptr;
+    double *fpart = nullptr;         // fused step: one row of FP64 totals per work item
+    int nfslots = 0;                 // rows of fpart
+    bool fold = false;               // the fused step accumulates the totals (FP32, no mask)
+    bool folded = false;             // fpart holds the totals of the state that entered the last step
+    double *htot = nullptr;          // mapped pinned host memory: the reduction tree's result
+    double *htot_dev = nullptr;      // its device address
+    int64_t steps = 0;               // steps since the last lbm_init_fields / lbm_set_populations
+    double last[5] = {0, 0, 0, 0, 0};  // the latest watchdog check: M, J, domain count
+    int64_t last_step = -1;          // the step index of the state those totals describe
+    double *rscratch = nullptr;      // intermediate rows of the reduction tree
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
     double *ptens = nullptr;         // FP64 pressure tensor output, D(D+1)/2 * N (on first use)
     void *pack = nullptr;            // contiguous staging of one field for padded rows (on first use)
@@ -71,27 +81,38 @@ const void *params_ptr(const lbm_ctx *c) { return c->fp64 ? (const void *)&c->pd
 void free_ctx(lbm_ctx *c) {
     if (!c) return;
     void *ptrs[] = {c->A, c->B, c->rho, c->gfl, c->mask, c->links, c->pflags, c->qlo, c->wall, c->lq, c->partials,
-                    c->totals, c->io, c->ptens, c->pack};
+                    c->io, c->ptens, c->pack, c->fpart, c->rscratch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (c->htot) (void)hipHostFree(c->htot);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
+}
+
+// reduction tree over partial rows -> host[5] (synchronous): the last level writes the
+// totals straight into mapped pinned host memory, so a check is the tree and a stream sync
+int reduce_rows(lbm_ctx *c, const double *rows, int n, double host[5]) {
+    launch_reduce(c->stream, rows, n, c->rscratch, c->htot_dev);
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 5; ++k) host[k] = c->htot[k];
+    return LBM_OK;
 }
 
 // mass/momentum of the current state -> host[5]; also the domain-error count
 int reduce_state(lbm_ctx *c, double host[5]) {
     c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
-    launch_reduce(c->stream, c->partials, c->nblk, c->totals);
-    HIP_OR_FAIL(c, hipGetLastError());
-    HIP_OR_FAIL(c, hipMemcpyAsync(host, c->totals, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    return LBM_OK;
+    return reduce_rows(c, c->partials, c->nblk, host);
 }
 
+// Watchdog check. After a single-pass step it reduces the rows that step wrote while pulling
+// its input state (no moment pass); otherwise it runs the moment pass on the current state.
 int watchdog(lbm_ctx *c) {
     double t[5];
-    int rc = reduce_state(c, t);
+    int rc = c->folded ? reduce_rows(c, c->fpart, c->nfslots, t) : reduce_state(c, t);
     if (rc) return rc;
+    for (int k = 0; k < 5; ++k) c->last[k] = t[k];
+    c->last_step = c->folded ? c->steps - 1 : c->steps;
     if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) || !isfinite(t[3])) {
         c->sticky = LBM_E_DIVERGED;
         return fail(c, LBM_E_DIVERGED, "non-finite mass or momentum (simulation diverged)");
@@ -110,8 +131,10 @@ void fused_step(lbm_ctx *c) {
 }
 
 int one_step(lbm_ctx *c) {
+    ++c->steps;
     if (c->fused) {
         fused_step(c);
+        c->folded = c->fold;
     } else {
         c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
@@ -263,11 +286,19 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
                     zb = ze;
                 }
             }
-            // one launch per round of work items (one item per CU)
+            // one launch per round of work items (one item per CU); every item of a step owns
+            // one row of the FP64 totals, numbered across the plane runs
             std::vector<FusedSeg> rounds;
-            for (const FusedSeg &sg : c->segs)
-                for (const FusedGrid &w : fused_windows(sg.fg, cus)) rounds.push_back({sg.fn, w});
+            int slot0 = 0;
+            for (const FusedSeg &sg : c->segs) {
+                for (FusedGrid w : fused_windows(sg.fg, cus)) {
+                    w.slot0 = slot0;
+                    rounds.push_back({sg.fn, w});
+                }
+                slot0 += sg.fg.items;
+            }
             c->segs = rounds;
+            c->nfslots = slot0;
             if (!c->segs.empty()) c->fused = c->segs[0].fn;
         }
     }
@@ -279,15 +310,26 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         return fail(nullptr, LBM_E_HIP, std::string("HIP initialisation failed: ") + hipGetErrorString(e));
     }
     c->stream = c->own;
+    for (FusedSeg &sg : c->segs) sg.fg.partials = nullptr;   // set once fpart exists
     const size_t pop = (size_t)c->Q * (size_t)c->g.qs * c->sbytes;
     if (hipMalloc(&c->A, pop) != hipSuccess || hipMalloc(&c->B, pop) != hipSuccess ||
         hipMalloc(&c->rho, N * cbytes) != hipSuccess || hipMalloc(&c->gfl, (size_t)c->D * N * cbytes) != hipSuccess ||
         hipMalloc((void **)&c->partials, (size_t)c->nblk * kPartialSlots * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&c->totals, 8 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->rscratch, (size_t)std::max(reduce_scratch_rows(c->nblk), reduce_scratch_rows(c->nfslots)) *
+                                             kPartialSlots * sizeof(double)) != hipSuccess ||
+        (c->nfslots && hipMalloc((void **)&c->fpart, (size_t)c->nfslots * kPartialSlots * sizeof(double)) != hipSuccess) ||
         hipMalloc((void **)&c->io, (size_t)(1 + c->D) * N * sizeof(double)) != hipSuccess) {
         free_ctx(c);
         return fail(nullptr, LBM_E_NOMEM, "device allocation failed (" + std::to_string(2 * pop >> 20) + " MiB of populations)");
     }
+    if (hipHostMalloc((void **)&c->htot, 8 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->htot_dev, c->htot, 0) != hipSuccess) {
+        free_ctx(c);
+        return fail(nullptr, LBM_E_NOMEM, "pinned host allocation of the watchdog totals failed");
+    }
+    // the FP32 single-pass kernels without mask accumulate the totals of their input state
+    c->fold = c->fused && !c->masked && !c->fp64 && c->nfslots > 0;
+    for (FusedSeg &sg : c->segs) sg.fg.partials = c->fold ? c->fpart : nullptr;
     if (p->rho_wall_field) {   // per-node wall densities (solid entries are the ones used)
         c->wall = c->fp64 ? (void *)upload_wall_field<double>(p->rho_wall_field, c->g)
                           : (void *)upload_wall_field<float>(p->rho_wall_field, c->g);
@@ -373,6 +415,8 @@ int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u) {
     HIP_OR_FAIL(c, hipGetLastError());
     c->sticky = 0;
     c->initialized = true;
+    c->folded = false;
+    c->steps = 0;
     double t[5];
     int rc = reduce_state(c, t);
     if (rc) return rc;
@@ -414,10 +458,13 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
         if (!c->fused)
             c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
-        if (c->fused)
+        if (c->fused) {
             fused_step(c);
-        else
+            c->folded = c->fold;
+        } else {
             c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        }
+        ++c->steps;
         HIP_OR_FAIL(c, hipEventRecord(ev[2], c->stream));
         HIP_OR_FAIL(c, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;
@@ -492,6 +539,14 @@ void lbm_destroy(lbm_ctx *c) {
 
 const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
+int lbm_last_check(const lbm_ctx *c, double out[5], int64_t *state_step) {
+    if (!c || !out) return LBM_E_INVAL;
+    if (c->last_step < 0) return LBM_E_STATE;
+    for (int k = 0; k < 5; ++k) out[k] = c->last[k];
+    if (state_step) *state_step = c->last_step;
+    return LBM_OK;
+}
+
 int lbm_set_stream(lbm_ctx *c, void *hip_stream) {
     if (!c) return fail(c, LBM_E_INVAL, "context is NULL");
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
@@ -523,6 +578,8 @@ int lbm_set_populations(lbm_ctx *c, const void *host) {
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     c->initialized = true;
     c->sticky = 0;
+    c->folded = false;
+    c->steps = 0;
     return watchdog(c);
 }
 

@@ -349,23 +349,30 @@ template <class S> __global__ __launch_bounds__(256) void k_fill_zero(S *__restr
         A[k] = S(0);
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partials, int nblocks,
-                                                double *__restrict__ totals) {
+// One level of the deterministic FP64 tree over partial rows of kPartialSlots values: block b
+// sums rows [b R, (b + 1) R) (R = 2048) into out[b]. Each thread adds its eight rows
+// t, t + 256, ... in order, then the block halves in LDS; the order depends only on n.
+constexpr int kReduceRows = 2048;
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ in, int n, double *__restrict__ out) {
     __shared__ double red[256][kPartialSlots];
     double acc[kPartialSlots] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += 256)
+    const long long r0 = (long long)blockIdx.x * kReduceRows;
+    for (int k = 0; k < kReduceRows / 256; ++k) {
+        const long long r = r0 + threadIdx.x + 256LL * k;
+        if (r < n)
 #pragma unroll
-        for (int k = 0; k < kPartialSlots; ++k) acc[k] += partials[(long long)b * kPartialSlots + k];
+            for (int q = 0; q < kPartialSlots; ++q) acc[q] += in[r * kPartialSlots + q];
+    }
 #pragma unroll
-    for (int k = 0; k < kPartialSlots; ++k) red[threadIdx.x][k] = acc[k];
+    for (int q = 0; q < kPartialSlots; ++q) red[threadIdx.x][q] = acc[q];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
 #pragma unroll
-            for (int k = 0; k < kPartialSlots; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+            for (int q = 0; q < kPartialSlots; ++q) red[threadIdx.x][q] += red[threadIdx.x + h][q];
         __syncthreads();
     }
-    if (threadIdx.x < kPartialSlots) totals[threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x < kPartialSlots) out[(long long)blockIdx.x * kPartialSlots + threadIdx.x] = red[0][threadIdx.x];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -445,8 +452,29 @@ KernelSet kernel_set(int D, bool fp64, bool masked) {
     return masked ? Launch<3, float, float, true>::set() : Launch<3, float, float, false>::set();
 }
 
-void launch_reduce(hipStream_t s, const double *partials, int nblocks, double *totals) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nblocks, totals);
+long long reduce_scratch_rows(int n) {
+    long long rows = 0;
+    for (long long m = n; m > 1;) {
+        m = (m + kReduceRows - 1) / kReduceRows;
+        rows += m;
+    }
+    return rows + 1;
+}
+
+void launch_reduce(hipStream_t s, const double *partials, int n, double *scratch, double *totals) {
+    // levels of k_reduce until one row is left; the intermediate rows go to consecutive
+    // regions of scratch, the last level writes totals
+    const double *src = partials;
+    double *dst = scratch;
+    long long m = n;
+    do {
+        const long long nb = (m + kReduceRows - 1) / kReduceRows;
+        double *out = nb == 1 ? totals : dst;
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, src, (int)m, out);
+        src = out;
+        dst += nb * kPartialSlots;
+        m = nb;
+    } while (m > 1);
 }
 
 }  // namespace lbm

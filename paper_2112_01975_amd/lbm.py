@@ -28,7 +28,7 @@ EXPORTED = [
     "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_surface_tension",
     "lbm_eos_pressure", "lbm_pressure_tensor", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
-    "lbm_batch_last_error",
+    "lbm_batch_last_error", "lbm_copy_probe", "lbm_last_check",
 ]
 
 
@@ -90,6 +90,8 @@ def lib() -> C.CDLL:
         L.lbm_batch_destroy.restype = None
         L.lbm_batch_last_error.argtypes = [vp]
         L.lbm_batch_last_error.restype = C.c_char_p
+        L.lbm_copy_probe.argtypes = [vp, vp, i64, C.c_int, vp, vp]
+        L.lbm_last_check.argtypes = [vp, vp, C.POINTER(i64)]
         _lib = L
     return _lib
 
@@ -197,6 +199,14 @@ def lbm_last_error(ctx=None) -> str:
     return (lib().lbm_last_error(ctx) or b"").decode()
 
 
+def lbm_last_check(ctx):
+    """(totals[4], domain count, step index of the state they describe) of the latest check."""
+    out = np.zeros(5)
+    st = C.c_int64()
+    _check(lib().lbm_last_check(ctx, _ptr(out), C.byref(st)), ctx)
+    return out[:4].copy(), int(out[4]), int(st.value)
+
+
 def lbm_set_stream(ctx, stream_handle: int | None):
     _check(lib().lbm_set_stream(ctx, stream_handle), ctx)
 
@@ -288,6 +298,15 @@ def lbm_batch_moments(b, icase: int, N: int, D: int):
     rho, U, tot = np.empty(N), np.empty((D, N)), np.empty(4)
     _check(lib().lbm_batch_moments(b, icase, _ptr(rho), _ptr(U), _ptr(tot)), b, batch=True)
     return rho, U, tot
+
+
+def lbm_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, reps: int = 5, stream_handle: int | None = None):
+    """Attainable copy bandwidth on device buffers (data pointers): (GB/s, ms per copy, shape code)."""
+    out = np.zeros(3)
+    rc = lib().lbm_copy_probe(dst_ptr, src_ptr, int(nbytes), int(reps), stream_handle, _ptr(out))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_copy_probe failed")
+    return float(out[0]), float(out[1]), int(out[2])
 
 
 def lbm_batch_destroy(b):

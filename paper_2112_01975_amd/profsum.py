@@ -7,7 +7,7 @@
 `stats` turns a --kernel-trace --stats summary into a short text table. `traffic`
 reads two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scales each
 counter by what it reads for the plain device copy of known size in the same run
-(the bench's copy probe), and prints HBM bytes per launch of the named kernel,
+(the bench's copy probe, lbm_copy_probe), and prints HBM bytes per launch of the named kernel,
 together with a fingerprint of the kernel sources so that a later run can tell
 whether the counters still describe the current kernel.
 """
@@ -71,9 +71,9 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, comman
             raise SystemExit(f"no dispatch matching {key!r}")
         return vals
 
-    # copy probe: the largest copy dispatches move copy_bytes each way
-    cf = max(pick(f, "copyBuffer")) * 1024.0
-    cw = max(pick(w, "copyBuffer")) * 1024.0
+    # copy probe (lbm_copy_probe's k_copy): its dispatches move copy_bytes each way
+    cf = max(pick(f, "k_copy")) * 1024.0
+    cw = max(pick(w, "k_copy")) * 1024.0
     fetch_scale = copy_bytes / cf
     write_scale = copy_bytes / cw
     kf = pick(f, kernel)

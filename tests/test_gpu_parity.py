@@ -263,6 +263,64 @@ def test_watchdog_reports_divergence_and_domain():
         assert ei.value.code == P.LBM_E_DOMAIN
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_watchdog_totals_folded_into_the_fused_step(precision, monkeypatch):
+    # in FP32 on a grid without mask the single-pass step accumulates the FP64 totals of its
+    # input state (one row per work item: ragged x tiles, several z-chunks and launch windows
+    # here), so the check after step k describes the state after k - 1 steps; FP64 checks run
+    # the moment pass on the state after k steps. Against the oracle's totals of the state
+    # described (FP64 to 1e-12; FP32 deviation storage within its rounding)
+    import paper_2112_01975_amd as P
+    from oracle import oracle as O
+    monkeypatch.setenv("LBM2P_FUSED_TZ", "12")
+    case = Case(3, 70, 24, 40, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(70, 24, 40, 7.0, rl, rv, 5.0, centre=(35.0, 12.0, 20.0), noise=1e-5, seed=1009)
+    u0 = np.zeros((3, case.N))
+    u0[0] = 0.02                                      # a net momentum to check
+    orc = O.Oracle(case.oracle_config()).init(rho0, u0)
+    ref = [orc.moments()[2]]
+    for _ in range(6):
+        ref.append(orc.step(1).moments()[2])
+    with P.Simulation(case.params(precision, rv if precision else 0.0, check_every=1)) as s:
+        s.init(rho0, u0)
+        tot, bad, st = P.lbm_last_check(s.ctx)        # the init check: a moment pass on state 0
+        assert st == 0 and bad == 0
+        for k in range(1, 7):
+            s.step(1)
+            tot, bad, st = P.lbm_last_check(s.ctx)
+            assert st == (k - 1 if precision == 1 else k) and bad == 0
+            M, J = ref[st][0], ref[st][1:]
+            tol = 1e-12 if precision == 0 else 2e-6
+            assert abs(tot[0] / M - 1) < tol, (k, tot[0], M)
+            assert np.abs(tot[1:] - J).max() < tol * M, (k, tot[1:], J)
+
+
+def test_watchdog_folded_domain_count_one_step_late():
+    # plain LBGK (ideal EOS, no force) with a strong velocity wave on 8^3: the state after two
+    # steps has 128 nodes with rho <= 0 (outside the domain; all |rho| > 0.5), per the oracle.
+    # The FP32 fused step's totals describe its input state, so the check after step 3
+    # reports exactly those nodes
+    import paper_2112_01975_amd as P
+    from oracle import oracle as O
+    n = 8
+    case = Case(3, n, n, n, eos=T.IDEAL, kappa=0.0, tau=0.8)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    u0 = np.zeros((3, n ** 3))
+    u0[0] = 0.9 * np.sin(2 * np.pi * x.ravel() / n)
+    r2 = O.Oracle(case.oracle_config()).init(np.ones(n ** 3), u0).step(2).moments()[0]
+    assert int((r2 <= 0).sum()) == 128
+    with P.Simulation(case.params(1, 1.0, check_every=1)) as s:
+        s.init(np.ones(n ** 3), u0)
+        s.step(1)
+        s.step(1)                                     # checks state 1: in the domain
+        with pytest.raises(P.LbmError) as ei:
+            s.step(1)
+        assert ei.value.code == P.LBM_E_DOMAIN
+        _, bad, st = P.lbm_last_check(s.ctx)
+        assert st == 2 and bad == 128
+
+
 @pytest.mark.parametrize("dims,masked", [((70, 36, 40), False), ((64, 8, 32), False), ((5, 3, 7), False),
                                          ((48, 20, 36), True)])
 def test_fused_step_matches_two_pass_fp32(dims, masked, monkeypatch):
