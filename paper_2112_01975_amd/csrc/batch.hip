@@ -7,13 +7,15 @@
 //            and LBGK (the same device functions as the single-case kernels), written to
 //            the other lattice.
 // Stepped design (default): one launch per phase (and lattice) and step covers every case,
-// each case split into blocks of kStepNodes nodes, so the cases of a sweep share all CUs;
-// the phases are ordered by the stream. Persistent design (LBM2P_BATCH_STEPPED=0): one
-// workgroup owns a case and runs its whole step loop with workgroup barriers only; its
-// workgroup size comes from a small autotuner (timed trial launches, cached per case list).
-// Either way a chunk of steps is captured once in a HIP graph that lbm_batch_step replays.
+// each case split into blocks of nodes, so the cases of a sweep share all CUs; the phases
+// are ordered by the stream. The block split (threads per block, nodes per thread) is tuned
+// per case list and kept in a cache file keyed by the GPU target. Persistent design
+// (LBM2P_BATCH_STEPPED=0): one workgroup owns a case and runs its whole step loop with
+// workgroup barriers only; its workgroup size is tuned the same way. Either way a chunk of
+// steps is captured once in a HIP graph that lbm_batch_step replays.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -155,36 +157,53 @@ __device__ void case_steps(const CaseDesc &cd, const Params<C> &p, int nsteps, i
 
 // Stepped design: one launch per phase (and lattice) and step over every case at once,
 // each case split into blocks of work items in proportion to its size, so that the
-// cases of a sweep share all CUs instead of one workgroup each.
+// cases of a sweep share all CUs instead of one workgroup each. A block has TPB threads
+// (the launch's block size) and each thread NPT nodes of its case: thread t of block k
+// takes nodes k TPB + t + m nk TPB, m < NPT (nk blocks per case). The split changes which
+// thread computes a node, never the node's arithmetic, so every split gives the same bits.
 struct Work {
     int c, k, nk;   // case, block of the case, blocks of the case
 };
-constexpr int kStepBlock = 256, kStepNodes = 256;   // threads per block, nodes per block (one per thread)
+constexpr int kStepMaxBlock = 256;   // largest threads per block of the stepped kernels
 
-template <int D, int PHASE>
-__global__ __launch_bounds__(kStepBlock) void k_batch_phase(const CaseDesc *__restrict__ cases,
-                                                           const Work *__restrict__ work, int st,
-                                                           const int *__restrict__ parity) {
+template <int D, int PHASE, int NPT>
+__global__ __launch_bounds__(kStepMaxBlock) void k_batch_phase(const CaseDesc *__restrict__ cases,
+                                                               const Work *__restrict__ work, int st,
+                                                               const int *__restrict__ parity) {
     const Work w = work[blockIdx.x];
     const CaseDesc cd = cases[w.c];
     const bool even = ((st + parity[w.c]) & 1) == 0;
-    const int stride = w.nk * kStepBlock;
+    const int tpb = (int)blockDim.x;
+    const int stride = w.nk * tpb;
+    const int n0 = w.k * tpb + (int)threadIdx.x;
     if (cd.fp64) {
         const double *A = (const double *)(even ? cd.A : cd.B);
         double *B = (double *)(even ? cd.B : cd.A);
-        for (int n = w.k * kStepBlock + threadIdx.x; n < cd.g.N; n += stride) {
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int n = n0 + m * stride;
+            if (n >= cd.g.N) break;
             if constexpr (PHASE == 1) phase1_node<D, double, double>(cd, cd.pd, A, n);
             else phase2_node<D, double, double>(cd, cd.pd, A, B, n);
         }
     } else {
         const float *A = (const float *)(even ? cd.A : cd.B);
         float *B = (float *)(even ? cd.B : cd.A);
-        for (int n = w.k * kStepBlock + threadIdx.x; n < cd.g.N; n += stride) {
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int n = n0 + m * stride;
+            if (n >= cd.g.N) break;
             if constexpr (PHASE == 1) phase1_node<D, float, float>(cd, cd.pf, A, n);
             else phase2_node<D, float, float>(cd, cd.pf, A, B, n);
         }
     }
 }
+
+// block splits the stepped design's tuner tries: (threads per block, nodes per thread)
+struct Split {
+    int tpb, npt;
+};
+constexpr Split kSplits[] = {{256, 1}, {128, 1}, {64, 1}, {256, 2}, {128, 2}, {64, 2}, {128, 4}, {64, 4}};
 
 // one kernel per lattice: the register budget of a D2Q9 sweep is not set by the D3Q27 body
 // (D3Q27 cases run with at most 256 threads, which leaves room for the 27-population body)
@@ -228,8 +247,13 @@ struct lbm_batch {
     hipGraphExec_t exec = nullptr;
     int block = 256, chunk = 200;
     bool stepped = true;             // stepped kernels over all cases; false: one workgroup per case
+    bool tuned = false;              // the block split (stepped) or workgroup size (persistent) is set
+    Split split{256, 1};             // stepped design: threads per block, nodes per thread
+    std::vector<int> order;          // cases, D2Q9 first, largest first
     Work *d_work2 = nullptr, *d_work3 = nullptr;
     int nw2 = 0, nw3 = 0;            // work items per lattice for the stepped kernels
+    size_t cap2 = 0, cap3 = 0;       // capacity of the work lists (the finest split)
+    std::string gfx;                 // the device's target name (tuning cache key)
     std::vector<int> initialized;
     std::string err;
 };
@@ -256,18 +280,26 @@ void free_batch(lbm_batch *b) {
     delete b;
 }
 
+template <int PHASE>
+void launch_phase(lbm_batch *b, int st) {
+    const dim3 tb(b->split.tpb);
+    auto go = [&](auto kern2, auto kern3) {
+        if (b->nw2) hipLaunchKernelGGL(kern2, dim3(b->nw2), tb, 0, b->stream, b->d_cases, b->d_work2, st, b->d_parity);
+        if (b->nw3) hipLaunchKernelGGL(kern3, dim3(b->nw3), tb, 0, b->stream, b->d_cases, b->d_work3, st, b->d_parity);
+    };
+    switch (b->split.npt) {
+    case 1: go(k_batch_phase<2, PHASE, 1>, k_batch_phase<3, PHASE, 1>); break;
+    case 2: go(k_batch_phase<2, PHASE, 2>, k_batch_phase<3, PHASE, 2>); break;
+    default: go(k_batch_phase<2, PHASE, 4>, k_batch_phase<3, PHASE, 4>); break;
+    }
+}
+
 int launch(lbm_batch *b, int nsteps, int block) {
     const int nc = (int)b->host.size();
     if (b->stepped) {
         for (int st = 0; st < nsteps; ++st) {
-            if (b->nw2) hipLaunchKernelGGL((k_batch_phase<2, 1>), dim3(b->nw2), dim3(kStepBlock), 0, b->stream,
-                                           b->d_cases, b->d_work2, st, b->d_parity);
-            if (b->nw3) hipLaunchKernelGGL((k_batch_phase<3, 1>), dim3(b->nw3), dim3(kStepBlock), 0, b->stream,
-                                           b->d_cases, b->d_work3, st, b->d_parity);
-            if (b->nw2) hipLaunchKernelGGL((k_batch_phase<2, 2>), dim3(b->nw2), dim3(kStepBlock), 0, b->stream,
-                                           b->d_cases, b->d_work2, st, b->d_parity);
-            if (b->nw3) hipLaunchKernelGGL((k_batch_phase<3, 2>), dim3(b->nw3), dim3(kStepBlock), 0, b->stream,
-                                           b->d_cases, b->d_work3, st, b->d_parity);
+            launch_phase<1>(b, st);   // every case's phase 1 before any phase 2 (stream order)
+            launch_phase<2>(b, st);
         }
         if (nsteps & 1)
             hipLaunchKernelGGL(k_flip_parity, dim3((nc + 255) / 256), dim3(256), 0, b->stream, b->d_parity, nc, nsteps);
@@ -291,6 +323,68 @@ std::string signature(const lbm_batch *b) {
     for (const auto &cd : b->host)
         s += std::to_string(cd.D) + ":" + std::to_string(cd.fp64) + ":" + std::to_string(cd.g.N) + ";";
     return s;
+}
+
+// Work lists of the stepped kernels for the split sp: each case in blocks of tpb npt nodes,
+// largest case first; uploaded into the lists allocated for the finest split
+int build_work(lbm_batch *b, Split sp) {
+    std::vector<Work> w2, w3;
+    const int per = sp.tpb * sp.npt;
+    for (int c : b->order) {
+        const int nk = std::max(1, (int)((b->host[c].g.N + per - 1) / per));
+        for (int k = 0; k < nk; ++k) (b->host[c].D == 2 ? w2 : w3).push_back(Work{c, k, nk});
+    }
+    if (w2.size() > b->cap2 || w3.size() > b->cap3) return LBM_E_INVAL;
+    if ((!w2.empty() && hipMemcpy(b->d_work2, w2.data(), w2.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!w3.empty() && hipMemcpy(b->d_work3, w3.data(), w3.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess))
+        return LBM_E_HIP;
+    b->nw2 = (int)w2.size();
+    b->nw3 = (int)w3.size();
+    b->split = sp;
+    return LBM_OK;
+}
+
+// 64-bit FNV-1a of the case-list signature: the key of a tuning-cache entry
+std::string sig_hash(const std::string &s) {
+    unsigned long long h = 1469598103934665603ull;
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    char buf[17];
+    snprintf(buf, sizeof buf, "%016llx", h);
+    return buf;
+}
+
+// The tuning cache (LBM2P_TUNE_CACHE names a text file): one line per tuned case list,
+//   <gfx target> <signature hash> <design: s | p> <a> <b>
+// stepped: a = threads per block, b = nodes per thread; persistent: a = workgroup size.
+bool cache_lookup(const lbm_batch *b, char design, int *a, int *bb) {
+    const char *path = getenv("LBM2P_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    const std::string key = sig_hash(signature(b));
+    char gfx[128], h[64], d[8];
+    int x = 0, y = 0;
+    bool found = false;
+    while (fscanf(f, "%127s %63s %7s %d %d", gfx, h, d, &x, &y) == 5)
+        if (b->gfx == gfx && key == h && d[0] == design) {
+            *a = x;
+            *bb = y;
+            found = true;   // the last entry for a key wins
+        }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const lbm_batch *b, char design, int a, int bb) {
+    const char *path = getenv("LBM2P_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %s %c %d %d\n", b->gfx.c_str(), sig_hash(signature(b)).c_str(), design, a, bb);
+    fclose(f);
 }
 
 }  // namespace
@@ -382,20 +476,24 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
         return cx > cy;
     });
     for (int c = 0; c < ncases; ++c) (b->host[c].D == 2 ? b->n2 : b->n3) += 1;
-    // work items of the stepped kernels: each case in blocks of kStepNodes nodes, largest first
-    std::vector<Work> w2, w3;
+    // work lists of the stepped kernels, sized for the finest split (64 threads, one node each)
+    b->order = order;
     for (int c : order) {
-        const int nk = std::max(1, (int)((b->host[c].g.N + kStepNodes - 1) / kStepNodes));
-        for (int k = 0; k < nk; ++k) (b->host[c].D == 2 ? w2 : w3).push_back(Work{c, k, nk});
+        const size_t nk = (size_t)std::max(1, (b->host[c].g.N + 63) / 64);
+        (b->host[c].D == 2 ? b->cap2 : b->cap3) += nk;
     }
-    b->nw2 = (int)w2.size();
-    b->nw3 = (int)w3.size();
-    if (b->nw2 && !(b->d_work2 = (Work *)dalloc(w2.size() * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
-    if (b->nw3 && !(b->d_work3 = (Work *)dalloc(w3.size() * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
-    if ((b->nw2 && hipMemcpy(b->d_work2, w2.data(), w2.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess) ||
-        (b->nw3 && hipMemcpy(b->d_work3, w3.data(), w3.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess)) {
-        free_batch(b);
-        return bfail(nullptr, LBM_E_HIP, "work list upload failed");
+    if (b->cap2 && !(b->d_work2 = (Work *)dalloc(b->cap2 * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    if (b->cap3 && !(b->d_work3 = (Work *)dalloc(b->cap3 * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
+    if (build_work(b, Split{256, 1})) { free_batch(b); return bfail(nullptr, LBM_E_HIP, "work list upload failed"); }
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            b->gfx = prop.gcnArchName;
+            const size_t colon = b->gfx.find(':');
+            if (colon != std::string::npos) b->gfx.resize(colon);
+        }
+        if (b->gfx.empty()) b->gfx = "unknown";
     }
     // LBM2P_BATCH_STEPPED=0: the persistent design (one workgroup per case)
     {
@@ -438,49 +536,109 @@ int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const doub
     return LBM_OK;
 }
 
+// Saves every case's current lattice (host copies) and its parity, to be restored after
+// timed trial steps.
+struct Saved {
+    std::vector<std::vector<char>> pops;
+    std::vector<int> par;
+};
+
+static int save_states(lbm_batch *b, Saved *sv) {
+    sv->pops.resize(b->host.size());
+    sv->par.resize(b->host.size());
+    BHIP(b, hipMemcpy(sv->par.data(), b->d_parity, sv->par.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t c = 0; c < b->host.size(); ++c) {
+        const CaseDesc &cd = b->host[c];
+        const size_t bytes = (size_t)(cd.D == 3 ? 27 : 9) * cd.g.qs * (cd.fp64 ? 8 : 4);
+        sv->pops[c].resize(bytes);
+        BHIP(b, hipMemcpy(sv->pops[c].data(), current_A(b, (int)c, sv->par[c]), bytes, hipMemcpyDeviceToHost));
+    }
+    return LBM_OK;
+}
+
+static int restore_states(lbm_batch *b, const Saved &sv) {
+    BHIP(b, hipMemcpy(b->d_parity, sv.par.data(), sv.par.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (size_t c = 0; c < b->host.size(); ++c)
+        BHIP(b, hipMemcpy(current_A(b, (int)c, sv.par[c]), sv.pops[c].data(), sv.pops[c].size(), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+// wall time of `steps` directly launched steps of the current configuration
+static int trial(lbm_batch *b, int steps, int block, double *sec) {
+    BHIP(b, hipStreamSynchronize(b->stream));
+    auto t0 = std::chrono::steady_clock::now();
+    if (launch(b, steps, block)) return bfail(b, LBM_E_HIP, "trial launch failed");
+    BHIP(b, hipStreamSynchronize(b->stream));
+    *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return LBM_OK;
+}
+
+// Picks the stepped design's block split, or the persistent design's workgroup size, once
+// per batch: an environment override first (LBM2P_BATCH_SPLIT="threads,nodes" or
+// LBM2P_BATCH_BLOCK), then the tuning cache, else timed trials of a few steps on the live
+// state, which is restored afterwards (results never depend on the choice); a tuned choice
+// is appended to the cache.
 static int autotune(lbm_batch *b) {
-    if (b->stepped) return LBM_OK;   // fixed blocks of kStepBlock threads
+    if (b->tuned) return LBM_OK;
+    b->tuned = true;
+    const int trial_steps = 20;
+    if (b->stepped) {
+        int a = 0, nb = 0;
+        const char *env = getenv("LBM2P_BATCH_SPLIT");
+        if (env && sscanf(env, "%d,%d", &a, &nb) == 2) {
+            for (const Split &sp : kSplits)
+                if (sp.tpb == a && sp.npt == nb) return build_work(b, sp) ? bfail(b, LBM_E_HIP, "work list upload failed") : LBM_OK;
+        }
+        if (cache_lookup(b, 's', &a, &nb))
+            for (const Split &sp : kSplits)
+                if (sp.tpb == a && sp.npt == nb) return build_work(b, sp) ? bfail(b, LBM_E_HIP, "work list upload failed") : LBM_OK;
+        Saved sv;
+        int rc = save_states(b, &sv);
+        if (rc) return rc;
+        Split best = kSplits[0];
+        double best_t = 1e30;
+        for (const Split &sp : kSplits) {
+            if (build_work(b, sp)) return bfail(b, LBM_E_HIP, "work list upload failed");
+            double t = 0.0;
+            if ((rc = trial(b, 2, b->block, &t)) || (rc = trial(b, trial_steps, b->block, &t))) return rc;
+            if (t < best_t) { best_t = t; best = sp; }
+        }
+        if ((rc = restore_states(b, sv))) return rc;
+        if (build_work(b, best)) return bfail(b, LBM_E_HIP, "work list upload failed");
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        cache_store(b, 's', best.tpb, best.npt);
+        return LBM_OK;
+    }
+    // LBM2P_BATCH_BLOCK: a fixed workgroup size, a multiple of 64 up to 1024 (others are ignored)
+    const char *env = getenv("LBM2P_BATCH_BLOCK");
+    const int fixed = env ? atoi(env) : 0;
+    if (fixed >= 64 && fixed <= 1024 && fixed % 64 == 0) { b->block = fixed; return LBM_OK; }
     const std::string sig = signature(b);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(sig);
         if (it != g_tune_cache.end()) { b->block = it->second; return LBM_OK; }
     }
-    // LBM2P_BATCH_BLOCK: a fixed workgroup size, a multiple of 64 up to 1024 (others are ignored)
-    const char *env = getenv("LBM2P_BATCH_BLOCK");
-    const int fixed = env ? atoi(env) : 0;
-    if (fixed >= 64 && fixed <= 1024 && fixed % 64 == 0) { b->block = fixed; return LBM_OK; }
-    // timed trials of a few steps on the live state, then the state is rewound: the trials
-    // run an even number of steps on copies taken and restored through the graph-free path
+    int a = 0, nb = 0;
+    if (cache_lookup(b, 'p', &a, &nb) && a >= 64 && a <= 1024 && a % 64 == 0) {
+        b->block = a;
+        return LBM_OK;
+    }
+    Saved sv;
+    int rc = save_states(b, &sv);
+    if (rc) return rc;
     int best = 256;
     double best_t = 1e30;
-    const int trial_steps = 20;
-    // save every case's current lattice
-    std::vector<std::vector<char>> save(b->host.size());
-    std::vector<int> par(b->host.size());
-    BHIP(b, hipMemcpy(par.data(), b->d_parity, par.size() * sizeof(int), hipMemcpyDeviceToHost));
-    for (size_t c = 0; c < b->host.size(); ++c) {
-        const CaseDesc &cd = b->host[c];
-        const size_t bytes = (size_t)(cd.D == 3 ? 27 : 9) * cd.g.qs * (cd.fp64 ? 8 : 4);
-        save[c].resize(bytes);
-        BHIP(b, hipMemcpy(save[c].data(), current_A(b, (int)c, par[c]), bytes, hipMemcpyDeviceToHost));
-    }
     for (int blk : {256, 512, 1024}) {
-        BHIP(b, hipStreamSynchronize(b->stream));
-        auto t0 = std::chrono::steady_clock::now();
-        if (launch(b, trial_steps, blk)) return bfail(b, LBM_E_HIP, "trial launch failed");
-        BHIP(b, hipStreamSynchronize(b->stream));
-        double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        double t = 0.0;
+        if ((rc = trial(b, trial_steps, blk, &t))) return rc;
         if (t < best_t) { best_t = t; best = blk; }
     }
-    // restore the states (trial steps were even: parity unchanged)
-    for (size_t c = 0; c < b->host.size(); ++c) {
-        const CaseDesc &cd = b->host[c];
-        BHIP(b, hipMemcpy(current_A(b, (int)c, par[c]), save[c].data(), save[c].size(), hipMemcpyHostToDevice));
-    }
+    if ((rc = restore_states(b, sv))) return rc;
     b->block = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[sig] = best;
+    cache_store(b, 'p', best, 0);
     return LBM_OK;
 }
 

@@ -506,6 +506,44 @@ def test_batched_force_models(stepped, monkeypatch):
         P.lbm_batch_destroy(b)
 
 
+def test_batch_block_splits_agree_bit_for_bit_and_tuning_is_cached(monkeypatch, tmp_path):
+    # the stepped design's block split (threads per block, nodes per thread) only moves nodes
+    # between threads: forced splits give the same bits; the tuner's choice is appended once to
+    # the cache file (keyed by GPU target and case list) and read back by the next batch
+    import paper_2112_01975_amd as P
+    monkeypatch.setenv("LBM2P_BATCH_CHUNK", "16")
+    cases = _sweep_cases(6)
+    plist = [c.params(1 if not sc.fp64 else 0, rv if not sc.fp64 else 0.0) for sc, c, _, rv in cases]
+
+    def run():
+        b = P.lbm_batch_create(plist)
+        try:
+            for i, (sc, c, rho0, rv) in enumerate(cases):
+                P.lbm_batch_init_fields(b, i, rho0)
+            P.lbm_batch_step(b, 37)
+            return [P.lbm_batch_moments(b, i, c.N, 2)[:2] for i, (sc, c, _, _) in enumerate(cases)]
+        finally:
+            P.lbm_batch_destroy(b)
+
+    out = {}
+    for split in ("256,1", "64,1", "128,2", "64,4"):
+        monkeypatch.setenv("LBM2P_BATCH_SPLIT", split)
+        out[split] = run()
+    for split in ("64,1", "128,2", "64,4"):
+        for (ra, Ua), (rb, Ub) in zip(out["256,1"], out[split]):
+            assert np.array_equal(ra, rb) and np.array_equal(Ua, Ub), split
+    monkeypatch.delenv("LBM2P_BATCH_SPLIT")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LBM2P_TUNE_CACHE", str(cache))
+    tuned = run()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0].startswith("gfx") and lines[0].split()[2] == "s"
+    again = run()
+    assert cache.read_text().splitlines() == lines          # read back, not tuned again
+    for (ra, Ua), (rb, Ub), (rc, Uc) in zip(out["256,1"], tuned, again):
+        assert np.array_equal(ra, rb) and np.array_equal(ra, rc) and np.array_equal(Ua, Uc)
+
+
 def test_batch_designs_agree_bit_for_bit(monkeypatch):
     # the stepped kernels and the persistent design run the same per-node device functions in
     # the same order, so every field agrees exactly: FP64 and FP32 cases, both lattices, a mask,
