@@ -152,8 +152,9 @@ def traffic_from_profile():
 def batch_sweep(P, torch, steps):
     """64 D2Q9 flat-interface cases, 4 x L with L log-spaced 128..2048 increasing with T/Tc in
     0.55..0.99 (vdW, kappa 0.02, a set for W = 4 at T/Tc = 0.55, tau 0.8; FP32 below T/Tc = 0.95,
-    FP64 above): the batch (a HIP graph per chunk of steps, each step one launch per phase over
-    every case) against the same cases stepped one by one through lbm_step."""
+    FP64 above): the batch (a HIP graph per chunk of steps; its layout, e.g. tiles of several
+    steps per launch, chosen by the library's tuner) against the same cases stepped one by one
+    through lbm_step."""
     import lbm_inputs as L
     base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.55, 0.02, 0.8)
     a = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
@@ -172,6 +173,7 @@ def batch_sweep(P, torch, steps):
     for i, r in enumerate(inits):
         P.lbm_batch_init_fields(b, i, r)
     P.lbm_batch_step(b, 20)                       # autotune + graph capture + warm-up
+    layout = P.lbm_batch_layout(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.lbm_batch_step(b, steps)
@@ -188,7 +190,7 @@ def batch_sweep(P, torch, steps):
             torch.cuda.synchronize()
             t_seq += time.perf_counter() - t0
     return {"cases": len(cases), "nodes": nodes, "steps": steps, "batched_s": t_batch, "one_by_one_s": t_seq,
-            "speedup": t_seq / t_batch, "batched_MLUPS": nodes * steps / t_batch / 1e6,
+            "speedup": t_seq / t_batch, "batched_MLUPS": nodes * steps / t_batch / 1e6, "layout": layout,
             "one_by_one_MLUPS": nodes * steps / t_seq / 1e6,
             "fp64_cases": sum(1 for c in cases if c.precision == P.LBM_FP64)}
 

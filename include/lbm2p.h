@@ -245,17 +245,28 @@ int lbm_eos_pressure(const lbm_params *p, const double *rho, int64_t n, double *
 int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa);
 
 /* Batched sweep: ncases independent simulations (each a full lbm_params,
- * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes) advanced together: each step is
- * one launch per phase covering every case, with each case split into blocks in
- * proportion to its size, and chunks of steps are captured in a HIP graph that
- * lbm_batch_step replays. Interpolated walls (link_q) are rejected with
- * LBM_E_INVAL. lbm_batch_step checks every case for divergence at its end. */
+ * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes, any force model) advanced together,
+ * with chunks of steps captured in a HIP graph that lbm_batch_step replays:
+ *   - D2Q9 cases whose tile (all rows, a strip of columns plus a halo of 3 columns per
+ *     step) fits in LDS advance several steps per launch in tiles;
+ *   - the other cases take one launch per phase and step covering all of them, each case
+ *     split into blocks in proportion to its size.
+ * The layout (steps per tile launch, tile columns, block split) is chosen at the first
+ * lbm_batch_step by timed trials on the live state, which is then restored; results do not
+ * depend on it (bit for bit). LBM2P_TUNE_CACHE names a text file that keeps the choice per
+ * GPU target and case list. Interpolated walls (link_q) and cases with (D+1) N >= 2^31 are
+ * rejected with LBM_E_INVAL. lbm_batch_step checks every case for divergence at its end. */
 int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out);
 int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const double *u);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 int lbm_batch_moments(lbm_batch *b, int icase, double *rho, double *U, double totals[4]);
 void lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
+/* The layout in use (after the first lbm_batch_step): out[0] = 1 for the stepped design (0:
+ * one workgroup per case), out[1] = threads per block (persistent: the workgroup size),
+ * out[2] = nodes per thread, out[3] = steps per tile launch (0: no case in tiles),
+ * out[4] = tile columns, out[5] = tiles. */
+int lbm_batch_layout(const lbm_batch *b, int out[6]);
 
 #ifdef __cplusplus
 }

@@ -49,23 +49,53 @@ struct CaseDesc {
 };
 
 // --------------------------------------------------------------- device part
-// phase 1 at node n: rho, signed psi and g = rho u^3 of the state in A into the case's fields
-template <int D, class S, class C>
-__device__ __forceinline__ void phase1_node(const CaseDesc &cd, const Params<C> &p, const S *A, int n) {
+// The per-node step functions see a case through a view: node indices, solid flags, the
+// pull gather, the field arrays, 1- and 2-ring neighbour indices and the store. GlobalView
+// addresses the case's device arrays; TileView a tile of a D2Q9 case held in LDS. Both
+// designs run the same arithmetic in the same order, so they give the same bits.
+template <int D, class S, class C> struct GlobalView {
+    const Geom &g;
+    const uint8_t *mask;
+    const S *A;
+    S *B;
+    C *frho, *fpsi, *fg;
+    struct Node {
+        int x, y, z;
+        Nbr<D> nb;
+    };
+    __device__ __forceinline__ Node node(int n) const {
+        const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
+        return Node{x, y, z, Nbr<D>(g, x, y, z)};
+    }
+    __device__ __forceinline__ bool solid(int n) const { return mask && mask[n]; }
+    __device__ __forceinline__ int global_index(int n) const { return n; }
+    __device__ __forceinline__ void gather_at(const Node &nd, int n, C (&h)[Lat<D>::Q]) const {
+        if (mask) gather<D, S, C, true>(A, g.qs, mask, nd.nb, n, h);
+        else gather<D, S, C, false>(A, g.qs, mask, nd.nb, n, h);
+    }
+    __device__ __forceinline__ int at1(const Node &nd, int cx, int cy, int cz) const { return nd.nb.at(cx, cy, cz); }
+    __device__ __forceinline__ int at2(const Node &nd, int cx, int cy, int cz) const {
+        const int x2 = wrapi(nd.x + 2 * cx, g.nx), y2 = wrapi(nd.y + 2 * cy, g.ny);
+        const int z2 = D == 3 ? wrapi(nd.z + 2 * cz, g.nz) : 0;
+        return x2 + g.nx * (y2 + g.ny * z2);
+    }
+    __device__ __forceinline__ C &rho(int n) const { return frho[n]; }
+    __device__ __forceinline__ C &psi(int n) const { return fpsi[n]; }
+    __device__ __forceinline__ C &gfield(int a, int n) const { return fg[a * g.N + n]; }
+    __device__ __forceinline__ void store(int i, int n, C v) const { st_at(B + i * g.qs, (unsigned)n, S(v)); }
+};
+
+// phase 1 at node n (view coordinates nd): rho, signed psi and g = rho u^3 of the current
+// state into the fields
+template <int D, class S, class C, class V>
+__device__ __forceinline__ void phase1_at(const V &v, const Params<C> &p, int n, const typename V::Node &nd) {
     constexpr int Q = Lat<D>::Q;
-    const Geom &g = cd.g;
-    const uint8_t *mask = cd.mask;
-    C *frho = (C *)cd.frho, *fpsi = (C *)cd.fpsi, *fg = (C *)cd.fg;
-    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
     C rho, ga[3] = {C(0), C(0), C(0)};
-    if (mask && mask[n]) {
-        rho = wall_density(p, n);
+    if (v.solid(n)) {
+        rho = wall_density(p, v.global_index(n));
     } else {
         C h[Q];
-        if (mask)
-            gather<D, S, C, true>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
-        else
-            gather<D, S, C, false>(A, g.qs, mask, Nbr<D>(g, x, y, z), n, h);
+        v.gather_at(nd, n, h);
         C sum, j[3];
         moments_of<D, C>(h, sum, j);
         rho = p.rho_ref + sum;
@@ -76,34 +106,27 @@ __device__ __forceinline__ void phase1_node(const CaseDesc &cd, const Params<C> 
             ga[a] = rho * ua * ua * ua;
         }
     }
-    frho[n] = rho;
-    fpsi[n] = signed_psi(p.eos, rho);
+    v.rho(n) = rho;
+    v.psi(n) = signed_psi(p.eos, rho);
 #pragma unroll
-    for (int a = 0; a < D; ++a) fg[a * g.N + n] = ga[a];
+    for (int a = 0; a < D; ++a) v.gfield(a, n) = ga[a];
 }
 
-// phase 2 at fluid node n: force from the fields, correction, equilibria, LBGK; A -> B
-template <int D, class S, class C>
-__device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> &p, const S *A, S *B, int n) {
+// phase 2 at fluid node n (view coordinates nd): force from the fields, correction,
+// equilibria, LBGK, store
+template <int D, class S, class C, class V>
+__device__ __forceinline__ void phase2_at(const V &v, const Params<C> &p, int n, const typename V::Node &nd) {
     constexpr int Q = Lat<D>::Q;
-    const Geom &g = cd.g;
-    const uint8_t *mask = cd.mask;
-    const C *frho = (const C *)cd.frho, *fpsi = (const C *)cd.fpsi, *fg = (const C *)cd.fg;
-    if (mask && mask[n]) return;
-    const int x = n % g.nx, t = n / g.nx, y = t % g.ny, z = t / g.ny;
-    const Nbr<D> nb(g, x, y, z);
-    const C rho = frho[n], spc = fpsi[n];
+    if (v.solid(n)) return;
+    const C rho = v.rho(n), spc = v.psi(n);
     C Fp[3] = {C(0), C(0), C(0)}, Fc[3] = {C(0), C(0), C(0)};
     static_for<1, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = Lat<D>::c(i, 0), cy = Lat<D>::c(i, 1), cz = Lat<D>::c(i, 2);
         constexpr int cls = cx * cx + cy * cy + cz * cz - 1;   // weight class of c_i
-        const int n1 = nb.at(cx, cy, cz);
-        const int x2 = wrapi(x + 2 * cx, g.nx), y2 = wrapi(y + 2 * cy, g.ny);
-        const int z2 = D == 3 ? wrapi(z + 2 * cz, g.nz) : 0;
-        const int n2 = x2 + g.nx * (y2 + g.ny * z2);
-        const C p1 = fabs(fpsi[n1]), p2 = fabs(fpsi[n2]);
-        const C r1 = frho[n1], r2 = frho[n2];
+        const int n1 = v.at1(nd, cx, cy, cz), n2 = v.at2(nd, cx, cy, cz);
+        const C p1 = fabs(v.psi(n1)), p2 = fabs(v.psi(n2));
+        const C r1 = v.rho(n1), r2 = v.rho(n2);
         const C tp = p.gw[cls][0] * p1 + p.gw[cls][1] * p2;   // 3w (G1 psi1 + G2 psi2)
         const C tc = p.gw[cls][2] * r1 + p.gw[cls][3] * r2;   // 3w (G3 rho1 + G4 rho2)
         static_for<0, D>([&](auto A_) {
@@ -117,10 +140,7 @@ __device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> 
 #pragma unroll
     for (int a = 0; a < D; ++a) Sf[a] = rho * p.accel[a] - (C(2) * spc * Fp[a] + rho * Fc[a]);
     C h[Q];
-    if (mask)
-        gather<D, S, C, true>(A, g.qs, mask, nb, n, h);
-    else
-        gather<D, S, C, false>(A, g.qs, mask, nb, n, h);
+    v.gather_at(nd, n, h);
     C drho, j[3];
     moments_of<D, C>(h, drho, j);
     const C rinv = rcp(rho);
@@ -130,14 +150,182 @@ __device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> 
     const C omega = omega_of(p, rho);
     const C cf = (C(1) - C(0.5) * omega) * C(0.5);
     C Phi[3] = {C(0), C(0), C(0)};
-    Phi[0] = cf * (fg[nb.at(1, 0, 0)] - fg[nb.at(-1, 0, 0)]);
-    Phi[1] = cf * (fg[g.N + nb.at(0, 1, 0)] - fg[g.N + nb.at(0, -1, 0)]);
-    if constexpr (D == 3) Phi[2] = cf * (fg[2 * g.N + nb.at(0, 0, 1)] - fg[2 * g.N + nb.at(0, 0, -1)]);
+    Phi[0] = cf * (v.gfield(0, v.at1(nd, 1, 0, 0)) - v.gfield(0, v.at1(nd, -1, 0, 0)));
+    Phi[1] = cf * (v.gfield(1, v.at1(nd, 0, 1, 0)) - v.gfield(1, v.at1(nd, 0, -1, 0)));
+    if constexpr (D == 3) Phi[2] = cf * (v.gfield(2, v.at1(nd, 0, 0, 1)) - v.gfield(2, v.at1(nd, 0, 0, -1)));
     collide<D, C>(h, rho, drho, u, Sf, Phi, omega);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        st_at(B + i * g.qs, (unsigned)n, S(h[i]));
+        v.store(i, n, h[i]);
     });
+}
+
+template <int D, class S, class C>
+__device__ __forceinline__ GlobalView<D, S, C> global_view(const CaseDesc &cd, const S *A, S *B) {
+    return GlobalView<D, S, C>{cd.g, cd.mask, A, B, (C *)cd.frho, (C *)cd.fpsi, (C *)cd.fg};
+}
+
+template <int D, class S, class C>
+__device__ __forceinline__ void phase1_node(const CaseDesc &cd, const Params<C> &p, const S *A, int n) {
+    const auto v = global_view<D, S, C>(cd, A, nullptr);
+    phase1_at<D, S, C>(v, p, n, v.node(n));
+}
+
+template <int D, class S, class C>
+__device__ __forceinline__ void phase2_node(const CaseDesc &cd, const Params<C> &p, const S *A, S *B, int n) {
+    const auto v = global_view<D, S, C>(cd, A, B);
+    if (!v.solid(n)) phase2_at<D, S, C>(v, p, n, v.node(n));
+}
+
+// ---------------------------------------------------------------- several steps per launch
+// A D2Q9 case whose full y extent fits in LDS is advanced S steps per launch in tiles of TX
+// columns: a workgroup loads its tile plus H = 3 S halo columns on each side (all rows,
+// y periodic inside the tile), steps them in LDS and writes back its own TX columns. A node
+// at step t + 1 depends on nodes at most three columns away at step t (one for the pull, two
+// for the ring stencils of the nodes it pulls from), so after s steps columns [3 s, W - 3 s)
+// of the tile (W = TX + 2 H) are exact and after S steps the tile's own columns are. Halo
+// columns are recomputed by the neighbouring tiles: the price of dropping 2 S - 1 launches.
+struct TileWork {
+    int c, x0, tx;   // case, first column, columns of the tile
+};
+
+template <class S, class C> struct TileView {
+    const S *A;      // LDS populations of the current state, [9][M]
+    S *B;            // LDS populations of the next state
+    C *frho, *fpsi, *fg;
+    const uint8_t *mask;   // LDS solid flags or nullptr
+    const int *col;        // LDS: global column of each tile column (wrapped)
+    int W, M, nx;          // tile width with halo, nodes, case width
+    // a node's column and the LDS offsets of rows y - 2 .. y + 2 (periodic in y)
+    struct Node {
+        int j;
+        int row[5];
+    };
+    __device__ __forceinline__ bool solid(int n) const { return mask && mask[n]; }
+    __device__ __forceinline__ int global_index(int n) const { return col[n % W] + nx * (n / W); }
+    __device__ __forceinline__ int at1(const Node &nd, int cx, int cy, int) const { return nd.row[2 + cy] + nd.j + cx; }
+    __device__ __forceinline__ int at2(const Node &nd, int cx, int cy, int) const {
+        return nd.row[2 + 2 * cy] + nd.j + 2 * cx;
+    }
+    // the same pull as the global gather: f_i(r) = A_i(r - c_i), or A_opp(i)(r) from a solid source
+    __device__ __forceinline__ void gather_at(const Node &nd, int n, C (&h)[9]) const {
+        static_for<0, 9>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i == 0) {
+                h[0] = C(A[n]);
+            } else {
+                const int src = at1(nd, -Lat<2>::c(i, 0), -Lat<2>::c(i, 1), 0);
+                h[i] = solid(src) ? C(A[opp<2>(i) * M + n]) : C(A[i * M + src]);
+            }
+        });
+    }
+    __device__ __forceinline__ C &rho(int n) const { return frho[n]; }
+    __device__ __forceinline__ C &psi(int n) const { return fpsi[n]; }
+    __device__ __forceinline__ C &gfield(int a, int n) const { return fg[a * M + n]; }
+    __device__ __forceinline__ void store(int i, int n, C v) const { B[i * M + n] = S(v); }
+};
+
+// LDS bytes of a tile of W x ny nodes: two population sets, rho, s psi, g_x, g_y, the column
+// map and solid flags
+__host__ __device__ constexpr long long tile_lds_bytes(int W, int ny, int sbytes) {
+    return (long long)W * ny * (22LL * sbytes + 1) + 4LL * W + 16;
+}
+
+// Tile threads: 4 row lanes of CL column lanes (CL = 64 or 128), so that a node's tile
+// coordinates need no division; row offsets are wrapped by adding or subtracting ny.
+__device__ __forceinline__ int wrap_row(int y, int ny) {
+    while (y < 0) y += ny;
+    while (y >= ny) y -= ny;
+    return y;
+}
+
+// nsteps steps of one tile of a case (storage S, compute C) in LDS
+template <class S, class C, int CL>
+__device__ __forceinline__ void tile_run(const CaseDesc *cd, const TileWork &w, int nsteps, bool even, char *lds) {
+    constexpr int NT = 4 * CL;
+    // the case's parameters in registers, read once
+    const Params<C> p = *(const Params<C> *)(sizeof(C) == 8 ? (const void *)&cd->pd : (const void *)&cd->pf);
+    const uint8_t *gmask = cd->mask;
+    const S *gA = (const S *)(even ? cd->A : cd->B);
+    S *gB = (S *)(even ? cd->B : cd->A);
+    const int ny = cd->g.ny, nx = cd->g.nx;
+    const long long qs = cd->g.qs;
+    const int H = 3 * nsteps, W = w.tx + 2 * H, M = W * ny;
+    S *pop0 = (S *)lds;
+    S *pop1 = pop0 + 9 * M;
+    C *frho = (C *)(pop1 + 9 * M);
+    C *fpsi = frho + M;
+    C *fg = fpsi + M;
+    int *col = (int *)(fg + 2 * M);
+    uint8_t *msk = gmask ? (uint8_t *)(col + W) : nullptr;
+    const int tc = threadIdx.x & (CL - 1), tr = threadIdx.x / CL;   // column lane, row lane
+    for (int j = threadIdx.x; j < W; j += NT) col[j] = wrapi(w.x0 - H + j, nx);
+    __syncthreads();
+    // the tile with its halo from the current lattice: rows (population, y) by the four row
+    // lanes, eight loads in flight per thread before any is stored
+    constexpr int U = 8;
+    const int rows = 9 * ny;
+    for (int r0 = tr; r0 < rows; r0 += 4 * U)
+        for (int j = tc; j < W; j += CL) {
+            S v[U];
+            const int gc = col[j];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + 4 * u;
+                if (r < rows) {
+                    const int i = r / ny, y = r - i * ny;
+                    v[u] = gA[i * qs + gc + nx * y];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + 4 * u;
+                if (r < rows) pop0[r * W + j] = v[u];   // (i ny + y) W + j = i M + y W + j
+            }
+        }
+    if (msk)
+        for (int y = tr; y < ny; y += 4)
+            for (int j = tc; j < W; j += CL) msk[y * W + j] = gmask[col[j] + nx * y];
+    __syncthreads();
+    S *cur = pop0, *nxt = pop1;
+    for (int st = 1; st <= nsteps; ++st) {
+        const TileView<S, C> v{cur, nxt, frho, fpsi, fg, msk, col, W, M, nx};
+        auto node = [&](int j, int y) __attribute__((always_inline)) {
+            typename TileView<S, C>::Node nd;
+            nd.j = j;
+#pragma unroll
+            for (int d = 0; d < 5; ++d) nd.row[d] = wrap_row(y + d - 2, ny) * W;
+            return nd;
+        };
+        // fields on columns [3 st - 2, W - 3 st + 2): the ring stencils of the exact columns
+        const int a1 = 3 * st - 2, b1 = W - a1;
+        for (int y = tr; y < ny; y += 4)
+            for (int j = a1 + tc; j < b1; j += CL) phase1_at<2, S, C>(v, p, y * W + j, node(j, y));
+        __syncthreads();
+        const int a2 = 3 * st, b2 = W - a2;
+        for (int y = tr; y < ny; y += 4)
+            for (int j = a2 + tc; j < b2; j += CL) phase2_at<2, S, C>(v, p, y * W + j, node(j, y));
+        __syncthreads();
+        S *t = cur; cur = nxt; nxt = t;
+    }
+    // the tile's own columns [H, H + tx) into the next lattice
+    for (int r = tr; r < rows; r += 4) {
+        const int i = r / ny, y = r - i * ny;
+        for (int j = tc; j < w.tx; j += CL) gB[i * qs + (w.x0 + j) + nx * y] = cur[r * W + H + j];
+    }
+}
+
+// one launch: nsteps steps of the tiles listed in work; launch index li selects the current
+// lattice of each case with its parity
+template <int CL>
+__global__ __launch_bounds__(4 * CL) void k_batch_tile(const CaseDesc *__restrict__ cases, const TileWork *__restrict__ work,
+                                                       int nsteps, int li, const int *__restrict__ parity) {
+    extern __shared__ __align__(16) char lds[];
+    const TileWork w = work[blockIdx.x];
+    const CaseDesc *cd = cases + w.c;
+    const bool even = ((li + parity[w.c]) & 1) == 0;
+    if (cd->fp64) tile_run<double, double, CL>(cd, w, nsteps, even, lds);
+    else tile_run<float, float, CL>(cd, w, nsteps, even, lds);
 }
 
 // the whole step loop of one case in one workgroup (persistent design)
@@ -219,9 +407,9 @@ __global__ __launch_bounds__(D == 2 ? 1024 : 256) void k_batch(const CaseDesc *_
 }
 
 // flips the per-case lattice parity after a launch of an odd number of steps
-__global__ void k_flip_parity(int *parity, int ncases, int nsteps) {
+__global__ void k_flip_parity(int *parity, const int *tiled, int ncases, int nsteps, int nlaunch) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncases) parity[c] = (parity[c] + nsteps) & 1;
+    if (c < ncases) parity[c] = (parity[c] + (tiled[c] ? nlaunch : nsteps)) & 1;
 }
 
 thread_local std::string g_batch_err;
@@ -252,6 +440,14 @@ struct lbm_batch {
     std::vector<int> order;          // cases, D2Q9 first, largest first
     Work *d_work2 = nullptr, *d_work3 = nullptr;
     int nw2 = 0, nw3 = 0;            // work items per lattice for the stepped kernels
+    // several steps per launch (D2Q9 cases whose tile fits in LDS): tile lists per precision
+    TileWork *d_tile = nullptr;      // tiles of both precisions (one launch)
+    int nt = 0;
+    size_t tcap = 0;
+    int tile_steps = 0, tile_tx = 0;  // steps per launch (0: no case tiled), tile columns
+    int tile_lanes = 64;             // column lanes of a tile workgroup (4 row lanes each)
+    size_t tlds = 0;                 // dynamic LDS of the tile launches (the largest tile)
+    int *d_tiled = nullptr;          // per case: 1 when the case runs in tiles
     size_t cap2 = 0, cap3 = 0;       // capacity of the work lists (the finest split)
     std::string gfx;                 // the device's target name (tuning cache key)
     std::vector<int> initialized;
@@ -296,13 +492,25 @@ void launch_phase(lbm_batch *b, int st) {
 
 int launch(lbm_batch *b, int nsteps, int block) {
     const int nc = (int)b->host.size();
+    const dim3 fg((nc + 255) / 256);
     if (b->stepped) {
         for (int st = 0; st < nsteps; ++st) {
             launch_phase<1>(b, st);   // every case's phase 1 before any phase 2 (stream order)
             launch_phase<2>(b, st);
         }
-        if (nsteps & 1)
-            hipLaunchKernelGGL(k_flip_parity, dim3((nc + 255) / 256), dim3(256), 0, b->stream, b->d_parity, nc, nsteps);
+        int nl = 0;
+        if (b->tile_steps > 0 && b->nt)
+            for (int k = 0; k < nsteps; k += b->tile_steps, ++nl) {
+                const int st = std::min(b->tile_steps, nsteps - k);
+                if (b->tile_lanes == 128)
+                    hipLaunchKernelGGL(k_batch_tile<128>, dim3(b->nt), dim3(512), b->tlds, b->stream, b->d_cases, b->d_tile,
+                                       st, nl, b->d_parity);
+                else
+                    hipLaunchKernelGGL(k_batch_tile<64>, dim3(b->nt), dim3(256), b->tlds, b->stream, b->d_cases, b->d_tile,
+                                       st, nl, b->d_parity);
+            }
+        if ((nsteps & 1) || (nl & 1))
+            hipLaunchKernelGGL(k_flip_parity, fg, dim3(256), 0, b->stream, b->d_parity, b->d_tiled, nc, nsteps, nl);
         return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
     }
     if (b->n2)
@@ -311,7 +519,8 @@ int launch(lbm_batch *b, int nsteps, int block) {
     if (b->n3)
         hipLaunchKernelGGL(k_batch<3>, dim3(b->n3), dim3(block < 256 ? block : 256), 0, b->stream, b->d_cases, b->d_order + b->n2, nc,
                            nsteps, b->d_parity);
-    if (nsteps & 1) hipLaunchKernelGGL(k_flip_parity, dim3((nc + 255) / 256), dim3(256), 0, b->stream, b->d_parity, nc, nsteps);
+    if (nsteps & 1)
+        hipLaunchKernelGGL(k_flip_parity, fg, dim3(256), 0, b->stream, b->d_parity, b->d_tiled, nc, nsteps, nsteps);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
@@ -325,21 +534,56 @@ std::string signature(const lbm_batch *b) {
     return s;
 }
 
-// Work lists of the stepped kernels for the split sp: each case in blocks of tpb npt nodes,
-// largest case first; uploaded into the lists allocated for the finest split
-int build_work(lbm_batch *b, Split sp) {
+// LDS budget of one tile workgroup (two workgroups per CU)
+constexpr long long kTileLdsMax = 65536;
+
+// Tile width of case c for the tiling (steps per launch, tile columns): the widest of tx,
+// tx/2, ... (at least 8 columns, at most the case's width) whose tile fits in the LDS budget;
+// 0 when none does or the case is not D2Q9 (it then takes the stepped kernels).
+int tile_width(const lbm_batch *b, int c, int steps, int tx) {
+    const CaseDesc &cd = b->host[c];
+    if (cd.D != 2 || steps <= 0) return 0;
+    for (int t = std::min(tx, cd.g.nx); t >= std::min(8, cd.g.nx); t /= 2)
+        if (tile_lds_bytes(t + 6 * steps, cd.g.ny, cd.fp64 ? 8 : 4) <= kTileLdsMax) return t;
+    return 0;
+}
+
+// Work lists for the split sp and the tiling (steps per launch, tile columns, column lanes of
+// a tile workgroup; steps 0: no tiles): tiled cases in tiles of tx columns, the others in blocks of tpb npt nodes for the
+// stepped kernels, largest case first; uploaded into the lists allocated at create
+int build_work(lbm_batch *b, Split sp, int steps = 0, int tx = 64, int lanes = 64) {
     std::vector<Work> w2, w3;
+    std::vector<TileWork> tl;
+    std::vector<int> tiled(b->host.size(), 0);
+    size_t lds = 0;
     const int per = sp.tpb * sp.npt;
     for (int c : b->order) {
-        const int nk = std::max(1, (int)((b->host[c].g.N + per - 1) / per));
-        for (int k = 0; k < nk; ++k) (b->host[c].D == 2 ? w2 : w3).push_back(Work{c, k, nk});
+        const CaseDesc &cd = b->host[c];
+        if (const int tw = tile_width(b, c, steps, tx)) {
+            tiled[c] = 1;
+            for (int x0 = 0; x0 < cd.g.nx; x0 += tw) {
+                const int t = std::min(tw, cd.g.nx - x0);
+                tl.push_back(TileWork{c, x0, t});
+                lds = std::max(lds, (size_t)tile_lds_bytes(t + 6 * steps, cd.g.ny, cd.fp64 ? 8 : 4));
+            }
+            continue;
+        }
+        const int nk = std::max(1, (int)((cd.g.N + per - 1) / per));
+        for (int k = 0; k < nk; ++k) (cd.D == 2 ? w2 : w3).push_back(Work{c, k, nk});
     }
-    if (w2.size() > b->cap2 || w3.size() > b->cap3) return LBM_E_INVAL;
+    if (w2.size() > b->cap2 || w3.size() > b->cap3 || tl.size() > b->tcap) return LBM_E_INVAL;
     if ((!w2.empty() && hipMemcpy(b->d_work2, w2.data(), w2.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess) ||
-        (!w3.empty() && hipMemcpy(b->d_work3, w3.data(), w3.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess))
+        (!w3.empty() && hipMemcpy(b->d_work3, w3.data(), w3.size() * sizeof(Work), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!tl.empty() && hipMemcpy(b->d_tile, tl.data(), tl.size() * sizeof(TileWork), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(b->d_tiled, tiled.data(), tiled.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return LBM_E_HIP;
     b->nw2 = (int)w2.size();
     b->nw3 = (int)w3.size();
+    b->nt = (int)tl.size();
+    b->tlds = lds;
+    b->tile_steps = tl.empty() ? 0 : steps;
+    b->tile_tx = tx;
+    b->tile_lanes = lanes == 128 ? 128 : 64;
     b->split = sp;
     return LBM_OK;
 }
@@ -357,33 +601,34 @@ std::string sig_hash(const std::string &s) {
 }
 
 // The tuning cache (LBM2P_TUNE_CACHE names a text file): one line per tuned case list,
-//   <gfx target> <signature hash> <design: s | p> <a> <b>
-// stepped: a = threads per block, b = nodes per thread; persistent: a = workgroup size.
-bool cache_lookup(const lbm_batch *b, char design, int *a, int *bb) {
+//   <gfx target> <signature hash> <design: s | p> <v0> <v1> <v2> <v3> <v4>
+// stepped: threads per block, nodes per thread, steps per tile launch (0: no tiles), tile
+// columns, tile column lanes; persistent: the workgroup size and four zeros.
+bool cache_lookup(const lbm_batch *b, char design, int (&v)[5]) {
     const char *path = getenv("LBM2P_TUNE_CACHE");
     if (!path || !*path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
     const std::string key = sig_hash(signature(b));
     char gfx[128], h[64], d[8];
-    int x = 0, y = 0;
+    int x[5];
     bool found = false;
-    while (fscanf(f, "%127s %63s %7s %d %d", gfx, h, d, &x, &y) == 5)
+    while (fscanf(f, "%127s %63s %7s %d %d %d %d %d", gfx, h, d, &x[0], &x[1], &x[2], &x[3], &x[4]) == 8)
         if (b->gfx == gfx && key == h && d[0] == design) {
-            *a = x;
-            *bb = y;
+            for (int k = 0; k < 5; ++k) v[k] = x[k];
             found = true;   // the last entry for a key wins
         }
     fclose(f);
     return found;
 }
 
-void cache_store(const lbm_batch *b, char design, int a, int bb) {
+void cache_store(const lbm_batch *b, char design, const int (&v)[5]) {
     const char *path = getenv("LBM2P_TUNE_CACHE");
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %s %c %d %d\n", b->gfx.c_str(), sig_hash(signature(b)).c_str(), design, a, bb);
+    fprintf(f, "%s %s %c %d %d %d %d %d\n", b->gfx.c_str(), sig_hash(signature(b)).c_str(), design, v[0], v[1], v[2], v[3],
+            v[4]);
     fclose(f);
 }
 
@@ -481,6 +726,13 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
     for (int c : order) {
         const size_t nk = (size_t)std::max(1, (b->host[c].g.N + 63) / 64);
         (b->host[c].D == 2 ? b->cap2 : b->cap3) += nk;
+    }
+    for (int c : order)   // the tile list sized for the narrowest tiles (8 columns)
+        if (b->host[c].D == 2) b->tcap += (size_t)(b->host[c].g.nx + 7) / 8;
+    if ((b->tcap && !(b->d_tile = (TileWork *)dalloc(b->tcap * sizeof(TileWork)))) ||
+        !(b->d_tiled = (int *)dalloc(ncases * sizeof(int)))) {
+        free_batch(b);
+        return bfail(nullptr, LBM_E_NOMEM, "device allocation failed");
     }
     if (b->cap2 && !(b->d_work2 = (Work *)dalloc(b->cap2 * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
     if (b->cap3 && !(b->d_work3 = (Work *)dalloc(b->cap3 * sizeof(Work)))) { free_batch(b); return bfail(nullptr, LBM_E_NOMEM, "device allocation failed"); }
@@ -583,30 +835,66 @@ static int autotune(lbm_batch *b) {
     b->tuned = true;
     const int trial_steps = 20;
     if (b->stepped) {
-        int a = 0, nb = 0;
-        const char *env = getenv("LBM2P_BATCH_SPLIT");
-        if (env && sscanf(env, "%d,%d", &a, &nb) == 2) {
+        auto valid_split = [](int tpb, int npt) {
             for (const Split &sp : kSplits)
-                if (sp.tpb == a && sp.npt == nb) return build_work(b, sp) ? bfail(b, LBM_E_HIP, "work list upload failed") : LBM_OK;
-        }
-        if (cache_lookup(b, 's', &a, &nb))
-            for (const Split &sp : kSplits)
-                if (sp.tpb == a && sp.npt == nb) return build_work(b, sp) ? bfail(b, LBM_E_HIP, "work list upload failed") : LBM_OK;
+                if (sp.tpb == tpb && sp.npt == npt) return true;
+            return false;
+        };
+        auto valid_tiles = [](int steps, int tx, int lanes) {
+            return steps >= 0 && steps <= 16 && (tx == 32 || tx == 64 || tx == 128 || tx == 256) &&
+                   (lanes == 64 || lanes == 128);
+        };
+        auto apply = [&](int tpb, int npt, int steps, int tx, int lanes) {
+            return build_work(b, Split{tpb, npt}, steps, tx, lanes) ? bfail(b, LBM_E_HIP, "work list upload failed")
+                                                                    : LBM_OK;
+        };
+        // environment overrides: LBM2P_BATCH_SPLIT="threads,nodes" and LBM2P_BATCH_TILE=
+        // "steps,columns[,lanes]" (steps 0: no tiles); either one fixes the choice, the other part
+        // taking its default
+        int v[5] = {256, 1, 0, 64, 64};
+        const char *es = getenv("LBM2P_BATCH_SPLIT"), *et = getenv("LBM2P_BATCH_TILE");
+        bool fixed = false;
+        if (es && sscanf(es, "%d,%d", &v[0], &v[1]) == 2 && valid_split(v[0], v[1])) fixed = true;
+        else { v[0] = 256; v[1] = 1; }
+        v[4] = 64;
+        if (et && sscanf(et, "%d,%d,%d", &v[2], &v[3], &v[4]) >= 2 && valid_tiles(v[2], v[3], v[4])) fixed = true;
+        else { v[2] = 0; v[3] = 64; v[4] = 64; }
+        if (fixed) return apply(v[0], v[1], v[2], v[3], v[4]);
+        if (cache_lookup(b, 's', v) && valid_split(v[0], v[1]) && valid_tiles(v[2], v[3], v[4]))
+            return apply(v[0], v[1], v[2], v[3], v[4]);
         Saved sv;
         int rc = save_states(b, &sv);
         if (rc) return rc;
-        Split best = kSplits[0];
+        auto time_config = [&](Split sp, int steps, int tx, int lanes, double *t) {
+            if (build_work(b, sp, steps, tx, lanes)) return bfail(b, LBM_E_HIP, "work list upload failed");
+            int r;
+            if ((r = trial(b, 2, b->block, t)) || (r = trial(b, trial_steps, b->block, t))) return r;
+            return LBM_OK;
+        };
+        // first the tiling (steps per launch, tile columns, lanes) with the default split, then
+        // the split of the cases left to the stepped kernels
+        const int tilings[][3] = {{0, 64, 64},   {2, 128, 64},  {4, 64, 64},   {4, 128, 64},  {4, 128, 128},
+                                  {4, 256, 128}, {8, 128, 64},  {8, 128, 128}, {8, 256, 128}, {16, 256, 128}};
+        int bs = 0, btx = 64, bl = 64;
         double best_t = 1e30;
-        for (const Split &sp : kSplits) {
-            if (build_work(b, sp)) return bfail(b, LBM_E_HIP, "work list upload failed");
+        for (const auto &tl : tilings) {
             double t = 0.0;
-            if ((rc = trial(b, 2, b->block, &t)) || (rc = trial(b, trial_steps, b->block, &t))) return rc;
-            if (t < best_t) { best_t = t; best = sp; }
+            if ((rc = time_config(kSplits[0], tl[0], tl[1], tl[2], &t))) return rc;
+            if (t < best_t) { best_t = t; bs = tl[0]; btx = tl[1]; bl = tl[2]; }
         }
+        Split best = kSplits[0];
+        if ((rc = build_work(b, best, bs, btx, bl))) return bfail(b, LBM_E_HIP, "work list upload failed");
+        if (b->nw2 || b->nw3)
+            for (const Split &sp : kSplits) {
+                double t = 0.0;
+                if ((rc = time_config(sp, bs, btx, bl, &t))) return rc;
+                if (t < best_t) { best_t = t; best = sp; }
+            }
         if ((rc = restore_states(b, sv))) return rc;
-        if (build_work(b, best)) return bfail(b, LBM_E_HIP, "work list upload failed");
+        if ((rc = apply(best.tpb, best.npt, bs, btx, bl))) return rc;
+        const int chosen[5] = {best.tpb, best.npt, bs, btx, bl};
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        cache_store(b, 's', best.tpb, best.npt);
+        cache_store(b, 's', chosen);
         return LBM_OK;
     }
     // LBM2P_BATCH_BLOCK: a fixed workgroup size, a multiple of 64 up to 1024 (others are ignored)
@@ -619,9 +907,9 @@ static int autotune(lbm_batch *b) {
         auto it = g_tune_cache.find(sig);
         if (it != g_tune_cache.end()) { b->block = it->second; return LBM_OK; }
     }
-    int a = 0, nb = 0;
-    if (cache_lookup(b, 'p', &a, &nb) && a >= 64 && a <= 1024 && a % 64 == 0) {
-        b->block = a;
+    int pv[5] = {0, 0, 0, 0, 0};
+    if (cache_lookup(b, 'p', pv) && pv[0] >= 64 && pv[0] <= 1024 && pv[0] % 64 == 0) {
+        b->block = pv[0];
         return LBM_OK;
     }
     Saved sv;
@@ -638,7 +926,8 @@ static int autotune(lbm_batch *b) {
     b->block = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[sig] = best;
-    cache_store(b, 'p', best, 0);
+    const int chosen[5] = {best, 0, 0, 0, 0};
+    cache_store(b, 'p', chosen);
     return LBM_OK;
 }
 
@@ -708,5 +997,16 @@ void lbm_batch_destroy(lbm_batch *b) {
 }
 
 const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+int lbm_batch_layout(const lbm_batch *b, int out[6]) {
+    if (!b || !out) return LBM_E_INVAL;
+    out[0] = b->stepped ? 1 : 0;
+    out[1] = b->stepped ? b->split.tpb : b->block;
+    out[2] = b->stepped ? b->split.npt : 0;
+    out[3] = b->stepped ? b->tile_steps : 0;
+    out[4] = b->stepped && b->tile_steps ? b->tile_tx : 0;
+    out[5] = b->stepped && b->tile_steps ? b->nt : 0;
+    return LBM_OK;
+}
 
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTED = [
     "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_surface_tension",
     "lbm_eos_pressure", "lbm_pressure_tensor", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
-    "lbm_batch_last_error", "lbm_copy_probe", "lbm_last_check",
+    "lbm_batch_last_error", "lbm_copy_probe", "lbm_last_check", "lbm_batch_layout",
 ]
 
 
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
         L.lbm_batch_last_error.restype = C.c_char_p
         L.lbm_copy_probe.argtypes = [vp, vp, i64, C.c_int, vp, vp]
         L.lbm_last_check.argtypes = [vp, vp, C.POINTER(i64)]
+        L.lbm_batch_layout.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -307,6 +308,14 @@ def lbm_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, reps: int = 5, strea
     if rc != LBM_OK:
         raise LbmError(rc, "lbm_copy_probe failed")
     return float(out[0]), float(out[1]), int(out[2])
+
+
+def lbm_batch_layout(b) -> dict:
+    """The batch's layout in use (see include/lbm2p.h)."""
+    out = np.zeros(6, dtype=np.int32)
+    _check(lib().lbm_batch_layout(b, _ptr(out)), b, batch=True)
+    keys = ("stepped", "threads_per_block", "nodes_per_thread", "tile_steps", "tile_columns", "tiles")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def lbm_batch_destroy(b):

@@ -544,6 +544,51 @@ def test_batch_block_splits_agree_bit_for_bit_and_tuning_is_cached(monkeypatch, 
         assert np.array_equal(ra, rb) and np.array_equal(ra, rc) and np.array_equal(Ua, Uc)
 
 
+def test_batch_tiles_of_several_steps_agree_bit_for_bit(monkeypatch):
+    # D2Q9 cases whose tile fits in LDS advance several steps per launch (tiles with a halo of
+    # three columns per step, recomputed by the neighbours); the same per-node functions run
+    # in LDS, so every tiling matches the stepped kernels bit for bit: FP32 and FP64 sweep cases,
+    # a masked FP64 channel (bounce-back and wall density inside the tile), a D3Q27 case that
+    # stays with the stepped kernels, 37 steps (graph chunks of 16 and a remainder, odd tile
+    # launches), and tiles wider than some cases
+    import paper_2112_01975_amd as P
+    monkeypatch.setenv("LBM2P_BATCH_CHUNK", "16")
+    sweep = _sweep_cases(5)
+    fl = T.Fluid(T.VDW, 0.02, 2 / 21, 0.8)
+    rv8, rl8, _ = T.coexistence(fl)
+    mask = np.zeros((5, 96), np.uint8)
+    mask[0] = 1
+    mask[4, 10:40] = 1
+    cm = Case(2, 96, 5, a=0.02, T_reduced=0.8, rho_wall=0.5 * (rv8 + rl8), mask=mask.ravel(), accel=(1e-5, 0.0, 0.0))
+    c3 = Case(3, 20, 18, 16, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+    rv3, rl3 = c3.coexistence()
+    cases = [c for _, c, _, _ in sweep] + [cm, c3]
+    inits = [r0 for _, _, r0, _ in sweep] + [L.random_state(cm.N, 2, rv8, rl8, 0.02, 77)[0],
+                                             L.drop(20, 18, 16, 5.0, rl3, rv3, 5.0, noise=1e-5, seed=6)]
+    plist = [c.params(1 if not sc.fp64 else 0, rv if not sc.fp64 else 0.0) for sc, c, _, rv in sweep]
+    plist += [cm.params(0), c3.params(1, rv3)]
+
+    def run(tile):
+        monkeypatch.setenv("LBM2P_BATCH_TILE", tile)
+        b = P.lbm_batch_create(plist)
+        try:
+            for i, r0 in enumerate(inits):
+                P.lbm_batch_init_fields(b, i, r0)
+            P.lbm_batch_step(b, 37)
+            return [P.lbm_batch_moments(b, i, c.N, c.lattice)[:2] for i, c in enumerate(cases)]
+        finally:
+            P.lbm_batch_destroy(b)
+
+    ref = run("0,64")
+    for tile in ("4,32", "3,64", "8,32", "16,128", "4,128,128", "5,256,128"):
+        got = run(tile)
+        for i, ((ra, Ua), (rb, Ub)) in enumerate(zip(ref, got)):
+            assert np.array_equal(ra, rb) and np.array_equal(Ua, Ub), (tile, i)
+    # and the masked channel against the oracle (FP64)
+    ro, Uo, _ = run_oracle(cm, inits[-2], None, 37)
+    assert max_rel(ref[-2][0], ro) < FP64_RHO_TOL and np.abs(ref[-2][1] - Uo).max() < FP64_U_TOL
+
+
 def test_batch_designs_agree_bit_for_bit(monkeypatch):
     # the stepped kernels and the persistent design run the same per-node device functions in
     # the same order, so every field agrees exactly: FP64 and FP32 cases, both lattices, a mask,
