@@ -153,6 +153,23 @@ int lbm_step(lbm_ctx *c, int64_t n);
  * Synchronous. */
 int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]);
 
+/* For callers that cannot allocate device memory or wait on the device: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The values of lbm_moments,
+ * bit for bit, written into caller-owned DEVICE buffers and only enqueued on the context
+ * stream: no allocation, no synchronisation, no host copy. rho: device [N] (nullable);
+ * U: device [D][N] (nullable); both in the user layout (rows of nx, x fastest). totals:
+ * device [5] (nullable) = the four FP64 totals of lbm_moments, then the number of fluid
+ * nodes whose density is outside the EOS domain. The moment pass's partial rows and the
+ * reduction tree's rows use one static 8 MiB array per device, held until the process ends:
+ * a grid whose moment pass has more than 209,610 workgroups (ceil(nx/64) ceil(ny/4) nz; a
+ * 256^3 grid has 65,536) is rejected with LBM_E_INVAL before anything is enqueued. Every
+ * call on a device shares that array and leaves its contents there (nothing in it needs to
+ * start at zero), so calls that overlap on one GPU (other streams, threads or contexts, not
+ * ordered with this call) race and give wrong results; calls ordered on one stream do not.
+ * LBM_E_STATE before lbm_init_fields; a failed launch is LBM_E_HIP (possibly reported by a
+ * later call, as for any asynchronous work). */
+int lbm_moments_noalloc(lbm_ctx *c, double *rho, double *U, double *totals);
+
 /* Discrete pressure tensor of the current state (Appendix E). P: host [D(D+1)/2][N]
  * (caller-owned), components xx, yy, xy for D2Q9 and xx, yy, zz, xy, xz, yz for D3Q27; zero
  * at solid nodes. Appendix E splits the discrete Korteweg force into one- and two-ring

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,13 @@
 #include "thermo_host.hpp"
 
 using namespace lbm;
+
+// Device scratch of lbm_moments_noalloc: the moment pass's partial rows followed by the
+// intermediate rows of the FP64 reduction tree. Every device the library runs on holds one
+// copy until the process ends. Host code never passes this name to a kernel or a copy: it
+// uses the address that hipGetSymbolAddress returns for the device (device_scratch below).
+constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 struct lbm_ctx {
     lbm_params p;
@@ -45,6 +53,7 @@ struct lbm_ctx {
     double last[5] = {0, 0, 0, 0, 0};  // the latest watchdog check: M, J, domain count
     int64_t last_step = -1;          // the step index of the state those totals describe
     double *rscratch = nullptr;      // intermediate rows of the reduction tree
+    double *scratch = nullptr;       // this device's static scratch (lbm_moments_noalloc), not owned
     double *io = nullptr;            // FP64 staging for init / output: (1 + D) * N
     double *ptens = nullptr;         // FP64 pressure tensor output, D(D+1)/2 * N (on first use)
     void *pack = nullptr;            // contiguous staging of one field for padded rows (on first use)
@@ -63,6 +72,26 @@ struct lbm_ctx {
 namespace {
 
 thread_local std::string g_create_err;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+
+// Address of the static scratch on device dev, which must be current: resolved on the first
+// request for that device, then kept (each device holds its own copy at its own address).
+hipError_t device_scratch(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = (double *)p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 int fail(lbm_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg; else g_create_err = msg;
@@ -310,6 +339,10 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         return fail(nullptr, LBM_E_HIP, std::string("HIP initialisation failed: ") + hipGetErrorString(e));
     }
     c->stream = c->own;
+    if ((e = device_scratch(c->device, &c->scratch)) != hipSuccess) {
+        free_ctx(c);
+        return fail(nullptr, LBM_E_HIP, std::string("address of the device scratch: ") + hipGetErrorString(e));
+    }
     for (FusedSeg &sg : c->segs) sg.fg.partials = nullptr;   // set once fpart exists
     const size_t pop = (size_t)c->Q * (size_t)c->g.qs * c->sbytes;
     if (hipMalloc(&c->A, pop) != hipSuccess || hipMalloc(&c->B, pop) != hipSuccess ||
@@ -508,6 +541,41 @@ int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]) {
                                          hipMemcpyDeviceToHost));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     }
+    return LBM_OK;
+}
+
+int lbm_moments_noalloc(lbm_ctx *c, double *rho, double *U, double *totals) {
+    if (!c) return fail(c, LBM_E_INVAL, "context is NULL");
+    // the moment pass writes one partial row per workgroup; the tree's levels follow them
+    const size_t rows = (size_t)c->nblk + (size_t)reduce_scratch_rows(c->nblk);
+    const size_t need = rows * kPartialSlots * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(c, LBM_E_INVAL, "lbm_moments_noalloc: the grid needs " + std::to_string(need) +
+                                        " bytes of scratch, more than its " + std::to_string(kScratchBytes) +
+                                        " (use lbm_moments)");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_moments_noalloc before lbm_init_fields");
+    double *part = c->scratch, *tree = c->scratch + (size_t)c->nblk * kPartialSlots;
+    c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, part);
+    if (totals) launch_reduce(c->stream, part, c->nblk, tree, totals);
+    if (rho || U) {
+        // unpadded rows: the output pass writes the caller's buffers (the context's staging
+        // takes a field the caller did not ask for); padded rows: staging, then a repack
+        const size_t N = (size_t)c->g.N;
+        const bool padded = c->g.px != c->g.nx;
+        c->ks.output(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl,
+                     (padded || !rho) ? c->io : rho, (padded || !U) ? c->io + N : U);
+        if (padded) {
+            const long long words = 2LL * c->g.nx, sp = 2LL * c->g.px, yz = (long long)c->g.ny * c->g.nz;
+            auto repack = [&](const double *src, double *dst, long long rows_) {
+                const dim3 grid((unsigned)((words * rows_ + 255) / 256));
+                hipLaunchKernelGGL(k_repitch, grid, dim3(256), 0, c->stream, (const uint32_t *)src, (uint32_t *)dst,
+                                   words, sp, words, rows_);
+            };
+            if (rho) repack(c->io, rho, yz);
+            if (U) repack(c->io + N, U, c->D * yz);   // the D components are consecutive in both layouts
+        }
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
     return LBM_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "lbm_step_timed", "lbm_velocities", "lbm_coexistence", "lbm_kappa_for_width", "lbm_surface_tension",
     "lbm_eos_pressure", "lbm_pressure_tensor", "lbm_batch_create",
     "lbm_batch_init_fields", "lbm_batch_step", "lbm_batch_moments", "lbm_batch_destroy",
-    "lbm_batch_last_error", "lbm_copy_probe", "lbm_last_check", "lbm_batch_layout",
+    "lbm_batch_last_error", "lbm_copy_probe", "lbm_last_check", "lbm_batch_layout", "lbm_moments_noalloc",
 ]
 
 
@@ -66,6 +66,7 @@ def lib() -> C.CDLL:
         L.lbm_init_fields.argtypes = [vp, vp, vp]
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_moments.argtypes = [vp, vp, vp, vp]
+        L.lbm_moments_noalloc.argtypes = [vp, vp, vp, vp]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_last_error.argtypes = [vp]
@@ -189,6 +190,11 @@ def lbm_moments(ctx, N: int, D: int, want_fields: bool = True):
     tot = np.empty(4)
     _check(lib().lbm_moments(ctx, _ptr(rho), _ptr(U), _ptr(tot)), ctx)
     return rho, U, tot
+
+
+def lbm_moments_noalloc(ctx, rho_dev: int | None, U_dev: int | None, totals_dev: int | None):
+    """Device addresses (e.g. torch data_ptr()) of float64 buffers [N], [D][N], [5]; enqueued only."""
+    _check(lib().lbm_moments_noalloc(ctx, rho_dev, U_dev, totals_dev), ctx)
 
 
 def lbm_destroy(ctx):
