@@ -35,7 +35,7 @@ extern "C" {
 #define LBM_E_NOMEM (-2)    /* device or host allocation failed */
 #define LBM_E_HIP (-3)      /* a HIP runtime call failed */
 #define LBM_E_DOMAIN (-4)   /* rho <= 0, b*rho >= 1 (outside the EOS domain) or no van der Waals loop */
-#define LBM_E_DIVERGED (-5) /* non-finite mass or momentum at a watchdog check */
+#define LBM_E_DIVERGED (-5) /* non-finite values at a watchdog check */
 #define LBM_E_STATE (-6)    /* call out of order (e.g. step before init) */
 
 enum { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
@@ -265,14 +265,16 @@ int lbm_kappa_for_width(const lbm_params *p, double width, double *kappa);
  * D2Q9 or D3Q27, FP64 or FP32_DEV, uneven sizes, any force model) advanced together,
  * with chunks of steps captured in a HIP graph that lbm_batch_step replays:
  *   - D2Q9 cases whose tile (all rows, a strip of columns plus a halo of 3 columns per
- *     step) fits in LDS advance several steps per launch in tiles;
+ *     step on each side) fits in LDS advance several steps per launch in tiles;
  *   - the other cases take one launch per phase and step covering all of them, each case
  *     split into blocks in proportion to its size.
- * The layout (steps per tile launch, tile columns, block split) is chosen at the first
+ * The layout (steps per tile launch, tile row width, block split) is chosen at the first
  * lbm_batch_step by timed trials on the live state, which is then restored; results do not
  * depend on it (bit for bit). LBM2P_TUNE_CACHE names a text file that keeps the choice per
  * GPU target and case list. Interpolated walls (link_q) and cases with (D+1) N >= 2^31 are
- * rejected with LBM_E_INVAL. lbm_batch_step checks every case for divergence at its end. */
+ * rejected with LBM_E_INVAL. At its end lbm_batch_step checks every case for divergence in
+ * one pass over all cases (non-finite stored populations at fluid nodes): LBM_E_DIVERGED names
+ * the first such case. */
 int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out);
 int lbm_batch_init_fields(lbm_batch *b, int icase, const double *rho, const double *u);
 int lbm_batch_step(lbm_batch *b, int64_t n);
@@ -282,7 +284,8 @@ const char *lbm_batch_last_error(const lbm_batch *b);
 /* The layout in use (after the first lbm_batch_step): out[0] = 1 for the stepped design (0:
  * one workgroup per case), out[1] = threads per block (persistent: the workgroup size),
  * out[2] = nodes per thread, out[3] = steps per tile launch (0: no case in tiles),
- * out[4] = tile columns, out[5] = tiles. */
+ * out[4] = tile row width (own columns plus 3 halo columns per step on each side, before a
+ * case's tiles are narrowed to fit LDS and evened out), out[5] = tiles. */
 int lbm_batch_layout(const lbm_batch *b, int out[6]);
 
 #ifdef __cplusplus

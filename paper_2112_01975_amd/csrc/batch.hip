@@ -261,28 +261,29 @@ __device__ __forceinline__ void tile_run(const CaseDesc *cd, const TileWork &w, 
     const int tc = threadIdx.x & (CL - 1), tr = threadIdx.x / CL;   // column lane, row lane
     for (int j = threadIdx.x; j < W; j += NT) col[j] = wrapi(w.x0 - H + j, nx);
     __syncthreads();
-    // the tile with its halo from the current lattice: rows (population, y) by the four row
-    // lanes, eight loads in flight per thread before any is stored
-    constexpr int U = 8;
+    // the tile with its halo from the current lattice, straight into LDS: rows (population,
+    // y) by the four row lanes, each wave copying 64 consecutive 4-byte words of a row per
+    // load (an FP64 value is two words), every load in flight before the single wait
     const int rows = 9 * ny;
-    for (int r0 = tr; r0 < rows; r0 += 4 * U)
-        for (int j = tc; j < W; j += CL) {
-            S v[U];
-            const int gc = col[j];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = r0 + 4 * u;
-                if (r < rows) {
-                    const int i = r / ny, y = r - i * ny;
-                    v[u] = gA[i * qs + gc + nx * y];
+    {
+        constexpr int WPV = (int)(sizeof(S) / 4);   // 4-byte words per value
+        const int words = W * WPV;                  // words of one tile row
+        const int lane0 = tc & ~63;                 // the wave's first column lane
+        for (int r = tr; r < rows; r += 4) {
+            const int i = r / ny, y = r - i * ny;
+            const char *grow = (const char *)(gA + i * qs + (long long)nx * y);
+            char *lrow = (char *)(pop0 + (long long)r * W);
+            for (int k0 = lane0; k0 < words; k0 += CL) {
+                const int k = k0 + (tc & 63);
+                if (k < words) {
+                    const int j = k / WPV, part = k - j * WPV;
+                    __builtin_amdgcn_global_load_lds((const void *)(grow + (long long)col[j] * (long long)sizeof(S) + 4 * part),
+                                                     (__attribute__((address_space(3))) void *)(lrow + 4 * k0), 4, 0, 0);
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = r0 + 4 * u;
-                if (r < rows) pop0[r * W + j] = v[u];   // (i ny + y) W + j = i M + y W + j
-            }
         }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the copies have landed
+    }
     if (msk)
         for (int y = tr; y < ny; y += 4)
             for (int j = tc; j < W; j += CL) msk[y * W + j] = gmask[col[j] + nx * y];
@@ -412,6 +413,30 @@ __global__ void k_flip_parity(int *parity, const int *tiled, int ncases, int nst
     if (c < ncases) parity[c] = (parity[c] + (tiled[c] ? nlaunch : nsteps)) & 1;
 }
 
+// End-of-call divergence check: the non-finite stored populations of every case's current
+// lattice (fluid nodes), kCheckBlocks workgroups per case; bad[c kCheckBlocks + k] receives
+// workgroup k's count, so the host sums a fixed set of integers.
+constexpr int kCheckBlocks = 16;
+__global__ __launch_bounds__(256) void k_batch_nonfinite(const CaseDesc *__restrict__ cases, const int *__restrict__ parity,
+                                                         int *__restrict__ bad) {
+    __shared__ int s_bad[4];
+    const int c = blockIdx.y;
+    const CaseDesc &cd = cases[c];
+    const char *L = (const char *)((parity[c] & 1) ? cd.B : cd.A);
+    const long long N = cd.g.N, qs = cd.g.qs, total = (cd.D == 3 ? 27LL : 9LL) * N;
+    int n_bad = 0;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < total; k += (long long)kCheckBlocks * 256) {
+        const long long i = k / N, n = k - i * N;
+        if (cd.mask && cd.mask[n]) continue;
+        const double v = cd.fp64 ? ((const double *)L)[i * qs + n] : (double)((const float *)L)[i * qs + n];
+        n_bad += isfinite(v) ? 0 : 1;
+    }
+    for (int o = 32; o > 0; o >>= 1) n_bad += __shfl_xor(n_bad, o, 64);
+    if ((threadIdx.x & 63) == 0) s_bad[threadIdx.x >> 6] = n_bad;
+    __syncthreads();
+    if (threadIdx.x == 0) bad[c * kCheckBlocks + blockIdx.x] = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
+}
+
 thread_local std::string g_batch_err;
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;   // case-list signature -> workgroup size
@@ -444,10 +469,11 @@ struct lbm_batch {
     TileWork *d_tile = nullptr;      // tiles of both precisions (one launch)
     int nt = 0;
     size_t tcap = 0;
-    int tile_steps = 0, tile_tx = 0;  // steps per launch (0: no case tiled), tile columns
+    int tile_steps = 0, tile_tx = 0;  // steps per launch (0: no case tiled), tile row width
     int tile_lanes = 64;             // column lanes of a tile workgroup (4 row lanes each)
     size_t tlds = 0;                 // dynamic LDS of the tile launches (the largest tile)
     int *d_tiled = nullptr;          // per case: 1 when the case runs in tiles
+    int *d_bad = nullptr;            // divergence check: non-finite counts per case and workgroup
     size_t cap2 = 0, cap3 = 0;       // capacity of the work lists (the finest split)
     std::string gfx;                 // the device's target name (tuning cache key)
     std::vector<int> initialized;
@@ -534,24 +560,33 @@ std::string signature(const lbm_batch *b) {
     return s;
 }
 
-// LDS budget of one tile workgroup (two workgroups per CU)
-constexpr long long kTileLdsMax = 65536;
+// LDS budget of one tile workgroup: two workgroups per CU in gfx950's 160 KB
+constexpr long long kTileLdsMax = 81920;
 
-// Tile width of case c for the tiling (steps per launch, tile columns): the widest of tx,
-// tx/2, ... (at least 8 columns, at most the case's width) whose tile fits in the LDS budget;
-// 0 when none does or the case is not D2Q9 (it then takes the stepped kernels).
-int tile_width(const lbm_batch *b, int c, int steps, int tx) {
+// Columns per tile of case c for the tiling (steps per launch, tile row width W: the tile's own
+// columns plus a halo of 3 columns per step on each side). Row widths that are multiples of a
+// wave's 64 column lanes keep every lane busy in the per-node loops. The own width is W - 6
+// steps (the case's width if smaller), W narrowed by 32 columns at a time until the tile fits
+// the LDS budget (at least 8 own columns), then evened out over the case's tiles; 0 when no
+// width fits or the case is not D2Q9 (it then takes the stepped kernels).
+int tile_width(const lbm_batch *b, int c, int steps, int W) {
     const CaseDesc &cd = b->host[c];
     if (cd.D != 2 || steps <= 0) return 0;
-    for (int t = std::min(tx, cd.g.nx); t >= std::min(8, cd.g.nx); t /= 2)
-        if (tile_lds_bytes(t + 6 * steps, cd.g.ny, cd.fp64 ? 8 : 4) <= kTileLdsMax) return t;
+    for (int w = W; w - 6 * steps >= 8; w -= 32) {
+        const int t = std::min(w - 6 * steps, cd.g.nx);
+        if (tile_lds_bytes(t + 6 * steps, cd.g.ny, cd.fp64 ? 8 : 4) <= kTileLdsMax) {
+            const int k = (cd.g.nx + t - 1) / t;   // tiles of the case
+            return (cd.g.nx + k - 1) / k;
+        }
+    }
     return 0;
 }
 
-// Work lists for the split sp and the tiling (steps per launch, tile columns, column lanes of
-// a tile workgroup; steps 0: no tiles): tiled cases in tiles of tx columns, the others in blocks of tpb npt nodes for the
-// stepped kernels, largest case first; uploaded into the lists allocated at create
-int build_work(lbm_batch *b, Split sp, int steps = 0, int tx = 64, int lanes = 64) {
+// Work lists for the split sp and the tiling (steps per launch, tile row width, column lanes of
+// a tile workgroup; steps 0: no tiles): tiled cases in tiles of tile_width columns, the others
+// in blocks of tpb npt nodes for the stepped kernels, largest case first; uploaded into the
+// lists allocated at create
+int build_work(lbm_batch *b, Split sp, int steps = 0, int tx = 128, int lanes = 64) {
     std::vector<Work> w2, w3;
     std::vector<TileWork> tl;
     std::vector<int> tiled(b->host.size(), 0);
@@ -604,12 +639,15 @@ std::string sig_hash(const std::string &s) {
 //   <gfx target> <signature hash> <design: s | p> <v0> <v1> <v2> <v3> <v4>
 // stepped: threads per block, nodes per thread, steps per tile launch (0: no tiles), tile
 // columns, tile column lanes; persistent: the workgroup size and four zeros.
+// cache key: the case list and the meaning of the tuned values (tile row widths)
+std::string cache_signature(const lbm_batch *b) { return "tile-rows;" + signature(b); }
+
 bool cache_lookup(const lbm_batch *b, char design, int (&v)[5]) {
     const char *path = getenv("LBM2P_TUNE_CACHE");
     if (!path || !*path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    const std::string key = sig_hash(signature(b));
+    const std::string key = sig_hash(cache_signature(b));
     char gfx[128], h[64], d[8];
     int x[5];
     bool found = false;
@@ -627,7 +665,7 @@ void cache_store(const lbm_batch *b, char design, const int (&v)[5]) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %s %c %d %d %d %d %d\n", b->gfx.c_str(), sig_hash(signature(b)).c_str(), design, v[0], v[1], v[2], v[3],
+    fprintf(f, "%s %s %c %d %d %d %d %d\n", b->gfx.c_str(), sig_hash(cache_signature(b)).c_str(), design, v[0], v[1], v[2], v[3],
             v[4]);
     fclose(f);
 }
@@ -730,7 +768,8 @@ int lbm_batch_create(const lbm_params *cases, int ncases, lbm_batch **out) {
     for (int c : order)   // the tile list sized for the narrowest tiles (8 columns)
         if (b->host[c].D == 2) b->tcap += (size_t)(b->host[c].g.nx + 7) / 8;
     if ((b->tcap && !(b->d_tile = (TileWork *)dalloc(b->tcap * sizeof(TileWork)))) ||
-        !(b->d_tiled = (int *)dalloc(ncases * sizeof(int)))) {
+        !(b->d_tiled = (int *)dalloc(ncases * sizeof(int))) ||
+        !(b->d_bad = (int *)dalloc((size_t)ncases * kCheckBlocks * sizeof(int)))) {
         free_batch(b);
         return bfail(nullptr, LBM_E_NOMEM, "device allocation failed");
     }
@@ -840,8 +879,8 @@ static int autotune(lbm_batch *b) {
                 if (sp.tpb == tpb && sp.npt == npt) return true;
             return false;
         };
-        auto valid_tiles = [](int steps, int tx, int lanes) {
-            return steps >= 0 && steps <= 16 && (tx == 32 || tx == 64 || tx == 128 || tx == 256) &&
+        auto valid_tiles = [](int steps, int width, int lanes) {
+            return steps >= 0 && steps <= 16 && width >= 32 && width <= 512 && width % 32 == 0 &&
                    (lanes == 64 || lanes == 128);
         };
         auto apply = [&](int tpb, int npt, int steps, int tx, int lanes) {
@@ -849,16 +888,16 @@ static int autotune(lbm_batch *b) {
                                                                     : LBM_OK;
         };
         // environment overrides: LBM2P_BATCH_SPLIT="threads,nodes" and LBM2P_BATCH_TILE=
-        // "steps,columns[,lanes]" (steps 0: no tiles); either one fixes the choice, the other part
-        // taking its default
-        int v[5] = {256, 1, 0, 64, 64};
+        // "steps,row width[,lanes]" (steps 0: no tiles); either one fixes the choice, the other
+        // part taking its default
+        int v[5] = {256, 1, 0, 128, 64};
         const char *es = getenv("LBM2P_BATCH_SPLIT"), *et = getenv("LBM2P_BATCH_TILE");
         bool fixed = false;
         if (es && sscanf(es, "%d,%d", &v[0], &v[1]) == 2 && valid_split(v[0], v[1])) fixed = true;
         else { v[0] = 256; v[1] = 1; }
         v[4] = 64;
         if (et && sscanf(et, "%d,%d,%d", &v[2], &v[3], &v[4]) >= 2 && valid_tiles(v[2], v[3], v[4])) fixed = true;
-        else { v[2] = 0; v[3] = 64; v[4] = 64; }
+        else { v[2] = 0; v[3] = 128; v[4] = 64; }
         if (fixed) return apply(v[0], v[1], v[2], v[3], v[4]);
         if (cache_lookup(b, 's', v) && valid_split(v[0], v[1]) && valid_tiles(v[2], v[3], v[4]))
             return apply(v[0], v[1], v[2], v[3], v[4]);
@@ -871,11 +910,12 @@ static int autotune(lbm_batch *b) {
             if ((r = trial(b, 2, b->block, t)) || (r = trial(b, trial_steps, b->block, t))) return r;
             return LBM_OK;
         };
-        // first the tiling (steps per launch, tile columns, lanes) with the default split, then
+        // first the tiling (steps per launch, tile row width, lanes) with the default split, then
         // the split of the cases left to the stepped kernels
-        const int tilings[][3] = {{0, 64, 64},   {2, 128, 64},  {4, 64, 64},   {4, 128, 64},  {4, 128, 128},
-                                  {4, 256, 128}, {8, 128, 64},  {8, 128, 128}, {8, 256, 128}, {16, 256, 128}};
-        int bs = 0, btx = 64, bl = 64;
+        const int tilings[][3] = {{0, 128, 64}, {3, 64, 64},  {4, 64, 64},   {3, 128, 64},  {4, 128, 64},
+                                  {5, 128, 64}, {4, 192, 64}, {6, 192, 64},  {4, 128, 128}, {8, 256, 64},
+                                  {8, 256, 128}};
+        int bs = 0, btx = 128, bl = 64;
         double best_t = 1e30;
         for (const auto &tl : tilings) {
             double t = 0.0;
@@ -954,14 +994,19 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
         left -= b->chunk;
     }
     if (left > 0 && launch(b, (int)left, b->block)) return bfail(b, LBM_E_HIP, "launch failed");
+    // divergence check of every case in one pass: non-finite stored populations
+    const int nc = (int)b->host.size();
+    hipLaunchKernelGGL(k_batch_nonfinite, dim3(kCheckBlocks, nc), dim3(256), 0, b->stream, b->d_cases, b->d_parity,
+                       b->d_bad);
+    BHIP(b, hipGetLastError());
+    std::vector<int> bad((size_t)nc * kCheckBlocks);
+    BHIP(b, hipMemcpyAsync(bad.data(), b->d_bad, bad.size() * sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
-    // FP64 watchdog over every case
-    for (size_t c = 0; c < b->host.size(); ++c) {
-        double t[4];
-        int rc = lbm_batch_moments(b, (int)c, nullptr, nullptr, t);
-        if (rc) return rc;
-        if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) || !isfinite(t[3]))
-            return bfail(b, LBM_E_DIVERGED, "case " + std::to_string(c) + " diverged");
+    for (int c = 0; c < nc; ++c) {
+        long long nb = 0;
+        for (int k = 0; k < kCheckBlocks; ++k) nb += bad[(size_t)c * kCheckBlocks + k];
+        if (nb) return bfail(b, LBM_E_DIVERGED, "case " + std::to_string(c) + " diverged (" + std::to_string(nb) +
+                                                    " non-finite populations)");
     }
     return LBM_OK;
 }

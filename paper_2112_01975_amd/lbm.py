@@ -320,7 +320,7 @@ def lbm_batch_layout(b) -> dict:
     """The batch's layout in use (see include/lbm2p.h)."""
     out = np.zeros(6, dtype=np.int32)
     _check(lib().lbm_batch_layout(b, _ptr(out)), b, batch=True)
-    keys = ("stepped", "threads_per_block", "nodes_per_thread", "tile_steps", "tile_columns", "tiles")
+    keys = ("stepped", "threads_per_block", "nodes_per_thread", "tile_steps", "tile_row_width", "tiles")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -580,7 +580,7 @@ def test_batch_tiles_of_several_steps_agree_bit_for_bit(monkeypatch):
             P.lbm_batch_destroy(b)
 
     ref = run("0,64")
-    for tile in ("4,32", "3,64", "8,32", "16,128", "4,128,128", "5,256,128"):
+    for tile in ("4,32", "3,64", "4,96", "8,32", "16,128", "4,192", "4,128,128", "5,256,128", "12,384,128"):
         got = run(tile)
         for i, ((ra, Ua), (rb, Ub)) in enumerate(zip(ref, got)):
             assert np.array_equal(ra, rb) and np.array_equal(Ua, Ub), (tile, i)
@@ -715,3 +715,23 @@ def test_padded_rows_match_the_oracle(dims, masked, monkeypatch):
         s.step(7)
         r2, _, _ = s.moments()
     assert np.array_equal(r1, r2)
+
+
+def test_batch_step_reports_the_diverged_case():
+    # a D2Q9 case started far from equilibrium at tau 0.51 with densities up to b rho = 0.97
+    # leaves the EOS domain and turns non-finite within a few steps (the oracle does within 15);
+    # the end-of-call check of lbm_batch_step names it, and a sane case beside it does not matter
+    import paper_2112_01975_amd as P
+    good = Case(2, 48, 4, a=0.02, T_reduced=0.8)
+    wild = Case(2, 32, 4, a=0.02, T_reduced=0.8, tau=0.51)
+    rv, rl = good.coexistence()
+    rng = np.random.default_rng(5)
+    b = P.lbm_batch_create([good.params(1, rv), wild.params(0)])
+    try:
+        P.lbm_batch_init_fields(b, 0, L.flat_slab(48, 4, 1, rl, rv, 4.0, noise=1e-4, seed=9))
+        P.lbm_batch_init_fields(b, 1, rng.uniform(0.2, 10.2, wild.N))
+        with pytest.raises(P.LbmError) as ei:
+            P.lbm_batch_step(b, 60)
+        assert ei.value.code == P.LBM_E_DIVERGED and "case 1" in str(ei.value), str(ei.value)
+    finally:
+        P.lbm_batch_destroy(b)
