@@ -374,6 +374,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 64-case batched sweep (with its case-by-case comparison)")
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 512^2, drop-impact and posts legs")
     ap.add_argument("--posts-only", action="store_true",
                     help="run only the tapered-posts leg (curved walls) and print its JSON line")
@@ -400,6 +402,9 @@ def main():
         return
     if args.pressure_only:
         print(json.dumps({"pressure_tensor_256": pressure_tensor_leg(P, torch, args.size)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch_sweep": batch_sweep(P, torch, args.batch_steps)}), flush=True)
         return
     if args.posts_only:
         base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
