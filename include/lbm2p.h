@@ -167,7 +167,10 @@ int lbm_moments(lbm_ctx *c, double *rho, double *U, double totals[4]);
  * start at zero), so calls that overlap on one GPU (other streams, threads or contexts, not
  * ordered with this call) race and give wrong results; calls ordered on one stream do not.
  * LBM_E_STATE before lbm_init_fields; a failed launch is LBM_E_HIP (possibly reported by a
- * later call, as for any asynchronous work). */
+ * later call, as for any asynchronous work). A captured call records the population lattice
+ * that is current at capture; the context alternates its two lattices every step, so a replay
+ * reports the current state after an even number of steps since the capture (or capture the
+ * call together with an even number of steps taken with check_every < 0). */
 int lbm_moments_noalloc(lbm_ctx *c, double *rho, double *U, double *totals);
 
 /* Discrete pressure tensor of the current state (Appendix E). P: host [D(D+1)/2][N]

@@ -99,3 +99,40 @@ def test_noalloc_scratch_limit():
         with pytest.raises(P.LbmError) as e:
             P.lbm_moments_noalloc(s.ctx, None, None, None)
         assert e.value.code == P.LBM_E_INVAL and "scratch" in str(e.value)
+
+
+def test_noalloc_captured_in_a_graph_replays_match_eager():
+    # the entry point only enqueues kernels on the context stream (no allocation, memset or wait),
+    # so it can be captured: a graph of one call, replayed after eager steps on the same stream,
+    # gives lbm_moments of the state at each replay, bit for bit (padded rows: the output pass,
+    # the staging and the repack are all in the graph). The graph holds the lattice that was
+    # current at capture and the context alternates its two lattices every step, so the replays
+    # come after even numbers of steps
+    import torch
+
+    import paper_2112_01975_amd as P
+    case = Case(2, 70, 30)
+    with _state(P, case, 0, 5, 1105) as s:
+        D, N = case.lattice, case.N
+        rho = torch.zeros(N, dtype=torch.float64, device="cuda:0")
+        U = torch.zeros((D, N), dtype=torch.float64, device="cuda:0")
+        tot = torch.zeros(5, dtype=torch.float64, device="cuda:0")
+        stream = torch.cuda.Stream()
+        P.lbm_set_stream(s.ctx, stream.cuda_stream)
+        try:
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                P.lbm_moments_noalloc(s.ctx, rho.data_ptr(), U.data_ptr(), tot.data_ptr())
+            for rep in range(3):
+                P.lbm_step(s.ctx, 8)                      # eager work between the replays
+                with torch.cuda.stream(stream):
+                    graph.replay()
+                stream.synchronize()
+                r_h, U_h, t_h = s.moments()
+                print(f"replay {rep}: totals {tot.cpu().numpy()}", flush=True)
+                assert np.array_equal(rho.cpu().numpy(), r_h), rep
+                assert np.array_equal(U.cpu().numpy().reshape(D, N), U_h.reshape(D, N)), rep
+                assert np.array_equal(tot.cpu().numpy()[:4], t_h), rep
+        finally:
+            P.lbm_set_stream(s.ctx, None)
