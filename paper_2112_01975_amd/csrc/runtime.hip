@@ -271,10 +271,13 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
         // planes after a five-plane prologue; items run in rounds of one per CU. The number
         // of chunks minimises rounds x (planes per chunk + 6), chunks of >= 16 planes: long
         // chunks, but no last round that leaves most CUs idle (288 tiles on 256 CUs in one
-        // chunk would take two full rounds' time for 1.1 rounds' work).
+        // chunk would take two full rounds' time for 1.1 rounds' work). Chunks stay within
+        // 320 planes: over longer marches neighbouring tiles drift apart in z and the halo
+        // lines they share leave L2 between the two reads (600^3: 600-plane chunks 14.7,
+        // 300-plane chunks 15.2 GLUPS).
         auto chunk = [&](int len) {
             long long best = 1, cost = -1;
-            for (long long nzc = 1; nzc <= std::max(1, len / 16); ++nzc) {
+            for (long long nzc = std::max(1, (len + 319) / 320); nzc <= std::max(1, len / 16); ++nzc) {
                 const long long rounds = (tiles * nzc + cus - 1) / cus;
                 const long long c = rounds * ((len + nzc - 1) / nzc + 6);
                 if (cost < 0 || c < cost) { cost = c; best = nzc; }
