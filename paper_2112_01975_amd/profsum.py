@@ -3,6 +3,7 @@
   python -m paper_2112_01975_amd.profsum stats <kernel_stats.csv> <command...>
   python -m paper_2112_01975_amd.profsum traffic <fetch_counter_collection.csv> <write_counter_collection.csv> \
          <kernel-substring> <copy-bytes> <command...>
+  python -m paper_2112_01975_amd.profsum counters <kernel-substring> <compute-units> <xcds> <csv>... -- <command...>
 
 `stats` turns a --kernel-trace --stats summary into a short text table. `traffic`
 reads two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scales each
@@ -97,6 +98,36 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, comman
     return "\n".join(lines) + "\n"
 
 
+def counters(kernel: str, cus: int, xccs: int, paths: list, command: str) -> str:
+    """Mean per dispatch of every counter in the --pmc runs' counter_collection.csv files for
+    the named kernel, and busy fractions: a sum over CUs (`_sum`, SQ_ACTIVE_INST_VALU,
+    SQ_BUSY_CU_CYCLES) divided by the CU count, or an average over instances (`_avr`), over
+    the active cycles of one XCD (GRBM_GUI_ACTIVE, which each pass collects, summed over the
+    `xccs` XCDs in the output)."""
+    lines = ["# rocprofv3 --pmc counters per dispatch (mean over the kernel's dispatches)",
+             f"# command: {command}", f"kernel: {kernel}", f"compute_units: {cus}", f"xcds: {xccs}"]
+    for path in paths:
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if kernel in r["Kernel_Name"]:
+                acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if not acc:
+            raise SystemExit(f"no dispatch of {kernel!r} in {path}")
+        mean = {k: sum(v) / len(v) for k, v in acc.items()}
+        gui = mean.get("GRBM_GUI_ACTIVE")
+        if gui:
+            gui /= xccs   # active cycles of one XCD
+        lines.append(f"## pass {os.path.basename(os.path.dirname(path)) or path} ({len(next(iter(acc.values())))} dispatches)")
+        for k in sorted(mean):
+            lines.append(f"{k}: {mean[k]:.6g}")
+            if gui and k != "GRBM_GUI_ACTIVE":
+                per_cu = k.endswith("_sum") or k in ("SQ_ACTIVE_INST_VALU", "SQ_BUSY_CU_CYCLES")
+                frac = mean[k] / (cus * gui) if per_cu else (mean[k] / gui if k.endswith("_avr") else None)
+                if frac is not None:
+                    lines.append(f"{k}_frac_of_active_cycles: {frac:.4f}")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str) -> dict:
     d = {}
     with open(path) as fh:
@@ -109,8 +140,15 @@ def read_traffic(path: str) -> dict:
 
 
 if __name__ == "__main__":
+    if len(sys.argv) < 2:
+        raise SystemExit(__doc__)
     if sys.argv[1] == "stats":
         sys.stdout.write(stats(sys.argv[2], " ".join(sys.argv[3:])))
+    elif sys.argv[1] == "counters":
+        # counters <kernel-substring> <compute-units> <xcds> <csv> [<csv> ...] -- <command...>
+        i = sys.argv.index("--")
+        sys.stdout.write(counters(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), sys.argv[5:i],
+                                  " ".join(sys.argv[i + 1:])))
     elif sys.argv[1] == "traffic":
         sys.stdout.write(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), " ".join(sys.argv[6:])))
     else:
