@@ -132,3 +132,42 @@ def test_velocity_sets_are_the_full_stencils():
             assert (c[:, 2] == 0).all()
         rows = set(map(tuple, c.tolist()))
         assert all(tuple(-v for v in r) in rows for r in rows)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU: --gpus N > 1 exits with a message before touching a device
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_profile_summaries_from_counter_files(tmp_path):
+    # the profile summaries: traffic scaled by the copy probe's own counter reading, and busy
+    # fractions over one XCD's active cycles (GRBM_GUI_ACTIVE is summed over the XCDs)
+    from paper_2112_01975_amd import profsum
+    hdr = '"Kernel_Name","Counter_Name","Counter_Value"\n'
+    f = tmp_path / "fetch.csv"
+    w = tmp_path / "write.csv"
+    # copy of 1 MiB reads 512 KiB by the counter (factor 2), writes 1024 KiB (factor 1)
+    f.write_text(hdr + '"k_copy<1>","FETCH_SIZE",512\n"k_fused3<float>","FETCH_SIZE",100\n'
+                 '"k_fused3<float>","FETCH_SIZE",300\n')
+    w.write_text(hdr + '"k_copy<1>","WRITE_SIZE",1024\n"k_fused3<float>","WRITE_SIZE",50\n')
+    d = {}
+    for line in profsum.traffic(str(f), str(w), "k_fused3", 1 << 20, "cmd").splitlines():
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    assert float(d["fetch_bytes_per_launch"]) == 200 * 1024 * 2
+    assert float(d["write_bytes_per_launch"]) == 50 * 1024
+    c = tmp_path / "pass" / "run_counter_collection.csv"
+    c.parent.mkdir()
+    c.write_text(hdr + '"k_fused3<float>","GRBM_GUI_ACTIVE",8000\n"k_fused3<float>","TA_BUSY_avr",750\n'
+                 '"k_fused3<float>","TD_TD_BUSY_sum",176000\n"k_other","TA_BUSY_avr",1\n')
+    out = profsum.counters("k_fused3", 256, 8, [str(c)], "cmd")
+    assert "TA_BUSY_avr_frac_of_active_cycles: 0.7500" in out
+    assert "TD_TD_BUSY_sum_frac_of_active_cycles: 0.6875" in out
