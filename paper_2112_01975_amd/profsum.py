@@ -4,6 +4,8 @@
   python -m paper_2112_01975_amd.profsum traffic <fetch_counter_collection.csv> <write_counter_collection.csv> \
          <kernel-substring> <copy-bytes> <command...>
   python -m paper_2112_01975_amd.profsum counters <kernel-substring> <compute-units> <xcds> <csv>... -- <command...>
+  python -m paper_2112_01975_amd.profsum stepfetch <fetch_counter_collection.csv> <kernel-substring> <copy-bytes> \
+         <steps> <algorithmic-read-bytes-per-step> <label>
 
 `stats` turns a --kernel-trace --stats summary into a short text table. `traffic`
 reads two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), scales each
@@ -128,6 +130,20 @@ def counters(kernel: str, cus: int, xccs: int, paths: list, command: str) -> str
     return "\n".join(lines) + "\n"
 
 
+def step_fetch(path: str, kernel: str, copy_bytes: int, steps: int, algorithmic: float, label: str) -> str:
+    """One FETCH_SIZE run of a size leg: the named kernel's fetched bytes summed over its
+    dispatches and divided by the steps the run took (a step may be several launches), scaled
+    by the copy probe's reading in the same run, against the algorithmic read bytes per step."""
+    rows = list(csv.DictReader(open(path)))
+    kern = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+    copy = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
+    if not kern or not copy:
+        raise SystemExit(f"no dispatches of {kernel!r} or of the copy probe in {path}")
+    scale = copy_bytes / (max(copy) * 1024.0)
+    per_step = sum(kern) * 1024.0 * scale / steps
+    return (f"{label:14s} {len(kern) / steps:13.1f} {per_step:21.0f} {per_step / algorithmic:18.3f}\n")
+
+
 def read_traffic(path: str) -> dict:
     d = {}
     with open(path) as fh:
@@ -149,6 +165,10 @@ if __name__ == "__main__":
         i = sys.argv.index("--")
         sys.stdout.write(counters(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), sys.argv[5:i],
                                   " ".join(sys.argv[i + 1:])))
+    elif sys.argv[1] == "stepfetch":
+        # stepfetch <counter_collection.csv> <kernel-substring> <copy-bytes> <steps> <algorithmic-bytes> <label>
+        sys.stdout.write(step_fetch(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]), float(sys.argv[6]),
+                                    sys.argv[7]))
     elif sys.argv[1] == "traffic":
         sys.stdout.write(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), " ".join(sys.argv[6:])))
     else:
