@@ -257,16 +257,22 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
     // LBM2P_FUSED_TX / _TY / _TZ override the tile shape and z-chunk length). By default
     // the z-chunks are as long as possible while every CU still gets a work item: each
     // chunk re-reads a four-plane z halo and runs a five-plane prologue.
-    if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0)) {
-        const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
-        int cus = 256;
-        {
-            int dev = 0, n = 0;
-            if (hipGetDevice(&dev) == hipSuccess &&
-                hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-                cus = n;
-        }
-        const long long tiles = (long long)((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty);
+    const int tx = env_int("LBM2P_FUSED_TX", 64), ty = env_int("LBM2P_FUSED_TY", 8);
+    int cus = 256;
+    {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+    }
+    const long long tiles = (long long)((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty);
+    // Small grids: a work item marches its planes one after another, so when even 16-plane
+    // z-chunks give fewer items than CUs, the two-pass step, parallel over all nodes, is
+    // faster (per step, FP32 at 32^3, 64^3, 96^3: 94, 90, 104 us single-pass against 17, 25,
+    // 84 two-pass; FP64 162, 178, 211 against 22, 50, 200; at 128^3 the single pass wins, 129
+    // against 162 FP32). LBM2P_FUSED=1 takes the single-pass step at any size.
+    const bool few_items = tiles * std::max(1, c->g.nz / 16) < cus;
+    if (c->D == 3 && !env_int("LBM2P_TWO_PASS", 0) && (!few_items || env_int("LBM2P_FUSED", 0))) {
         // Chunk length for a run of len planes. Each work item (tile x chunk) marches its
         // planes after a five-plane prologue; items run in rounds of one per CU. The number
         // of chunks minimises rounds x (planes per chunk + 6), chunks of >= 16 planes: long

@@ -28,3 +28,14 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _single_pass_step_at_every_size(request, monkeypatch):
+    """GPU tests run the single-pass D3Q27 step on their small grids too (LBM2P_FUSED=1), as the
+    library takes it on large ones; by default small grids take the two-pass step. Tests of
+    that size rule remove the variable themselves."""
+    if "gpu" in request.keywords:
+        monkeypatch.setenv("LBM2P_FUSED", "1")
+    yield
+

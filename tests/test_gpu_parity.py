@@ -735,3 +735,23 @@ def test_batch_step_reports_the_diverged_case():
         assert ei.value.code == P.LBM_E_DIVERGED and "case 1" in str(ei.value), str(ei.value)
     finally:
         P.lbm_batch_destroy(b)
+
+
+def test_small_grids_take_the_two_pass_step_by_default(monkeypatch):
+    # By default a D3Q27 grid takes the single-pass step only when 16-plane z-chunks of its 64x8
+    # tiles give at least one work item per CU: 64^3 gives 32 (two-pass), 128^3 gives 256
+    # (single-pass). The default step at 64^3 matches the oracle (FP64, 20 steps).
+    import paper_2112_01975_amd as P
+    monkeypatch.delenv("LBM2P_FUSED", raising=False)
+    for n, single_pass in ((64, False), (128, True)):
+        case = Case(3, n, n, n, eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)
+        rv, rl = case.coexistence()
+        rho0 = L.drop(n, n, n, n / 4, rl, rv, 5.0, noise=1e-5, seed=7)
+        with P.Simulation(case.params(0)) as s:
+            s.init(rho0)
+            _, nl = P.lbm_step_timed(s.ctx, 20)
+            assert (nl[0] == 0) == single_pass, (n, list(nl))
+            if n == 64:
+                r_g, U_g, _ = s.moments()
+                r_o, U_o, _ = run_oracle(case, rho0, None, 20)
+                assert max_rel(r_g, r_o) <= FP64_RHO_TOL and np.abs(U_g - U_o).max() <= FP64_U_TOL
