@@ -414,18 +414,18 @@ __global__ void k_flip_parity(int *parity, const int *tiled, int ncases, int nst
 }
 
 // End-of-call divergence check: the non-finite stored populations of every case's current
-// lattice (fluid nodes), kCheckBlocks workgroups per case; bad[c kCheckBlocks + k] receives
-// workgroup k's count, so the host sums a fixed set of integers.
+// lattice (fluid nodes), kCheckBlocks workgroups per case (workgroup b: case b / kCheckBlocks);
+// bad[b] receives workgroup b's count, so the host sums a fixed set of integers.
 constexpr int kCheckBlocks = 16;
 __global__ __launch_bounds__(256) void k_batch_nonfinite(const CaseDesc *__restrict__ cases, const int *__restrict__ parity,
                                                          int *__restrict__ bad) {
     __shared__ int s_bad[4];
-    const int c = blockIdx.y;
+    const int c = blockIdx.x / kCheckBlocks, k0 = blockIdx.x % kCheckBlocks;
     const CaseDesc &cd = cases[c];
     const char *L = (const char *)((parity[c] & 1) ? cd.B : cd.A);
     const long long N = cd.g.N, qs = cd.g.qs, total = (cd.D == 3 ? 27LL : 9LL) * N;
     int n_bad = 0;
-    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < total; k += (long long)kCheckBlocks * 256) {
+    for (long long k = (long long)k0 * 256 + threadIdx.x; k < total; k += (long long)kCheckBlocks * 256) {
         const long long i = k / N, n = k - i * N;
         if (cd.mask && cd.mask[n]) continue;
         const double v = cd.fp64 ? ((const double *)L)[i * qs + n] : (double)((const float *)L)[i * qs + n];
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_batch_nonfinite(const CaseDesc *__restr
     for (int o = 32; o > 0; o >>= 1) n_bad += __shfl_xor(n_bad, o, 64);
     if ((threadIdx.x & 63) == 0) s_bad[threadIdx.x >> 6] = n_bad;
     __syncthreads();
-    if (threadIdx.x == 0) bad[c * kCheckBlocks + blockIdx.x] = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
+    if (threadIdx.x == 0) bad[blockIdx.x] = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
 }
 
 thread_local std::string g_batch_err;
@@ -996,8 +996,8 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
     if (left > 0 && launch(b, (int)left, b->block)) return bfail(b, LBM_E_HIP, "launch failed");
     // divergence check of every case in one pass: non-finite stored populations
     const int nc = (int)b->host.size();
-    hipLaunchKernelGGL(k_batch_nonfinite, dim3(kCheckBlocks, nc), dim3(256), 0, b->stream, b->d_cases, b->d_parity,
-                       b->d_bad);
+    hipLaunchKernelGGL(k_batch_nonfinite, dim3((unsigned)(kCheckBlocks * nc)), dim3(256), 0, b->stream, b->d_cases,
+                       b->d_parity, b->d_bad);
     BHIP(b, hipGetLastError());
     std::vector<int> bad((size_t)nc * kCheckBlocks);
     BHIP(b, hipMemcpyAsync(bad.data(), b->d_bad, bad.size() * sizeof(int), hipMemcpyDeviceToHost, b->stream));
