@@ -3,7 +3,7 @@
 Bar: FP64 storage within 1e-10 of the oracle, node by node, in density (relative) and
 flow velocity (absolute, lattice units) after 1000 steps (eq LBGK iterated); FP32
 deviation storage against the same oracle state with the pointwise bound stated per
-case. Two shapes of the 3D workloads:
+case. Three shapes of the 3D workloads:
   - the static drop (Peng-Robinson, T/Tc = 0.6, density ratio 853, W = 5, radius 16);
   - the drop impact on a pillar-textured floor (square pillars 8 wide, gap 8, 16 high,
     as in the 512 x 256 x 256 impact box), two viscosities nu_v = 15 nu_l with
