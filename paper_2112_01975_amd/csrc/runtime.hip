@@ -61,6 +61,9 @@ struct lbm_ctx {
     Params<double> pd{};
     Params<float> pf{};
     KernelSet ks{};
+    hipGraphExec_t gexec = nullptr;  // two-pass path: kGraphSteps steps captured once, replayed
+    void *gA = nullptr;              // the lattice those captured steps start from
+    bool use_graph = false;
     FusedLaunch fused = nullptr;     // single-pass step when available (D3Q27): the first segment's kernel
     std::vector<FusedSeg> segs;      // the launches of one fused step, over disjoint plane ranges
     bool initialized = false;
@@ -114,6 +117,7 @@ void free_ctx(lbm_ctx *c) {
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->htot) (void)hipHostFree(c->htot);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }
@@ -169,6 +173,62 @@ int one_step(lbm_ctx *c) {
         c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
     }
     void *t = c->A; c->A = c->B; c->B = t;
+    return LBM_OK;
+}
+
+// Two-pass steps per captured graph. Even, so that a replay leaves the two lattices in the
+// roles it found them in; 32 steps (64 kernels) make the host's launch cost per step small
+// next to a grid's own time down to a few thousand nodes.
+constexpr int kGraphSteps = 32;
+
+// Captures kGraphSteps two-pass steps from the current lattice on the context's own stream
+// (never the caller's, which may itself be capturing). The graph holds kernels only.
+int capture_steps(lbm_ctx *c) {
+    HIP_OR_FAIL(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+    void *a = c->A, *b = c->B;
+    for (int s = 0; s < kGraphSteps; ++s) {
+        c->ks.moments(c->own, a, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+        c->ks.collide(c->own, a, b, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        std::swap(a, b);
+    }
+    const hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->own, &graph);
+    hipError_t ie = hipSuccess;
+    if (le == hipSuccess && ee == hipSuccess) ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);   // the executable graph does not need it
+    const hipError_t e = le != hipSuccess ? le : (ee != hipSuccess ? ee : ie);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, LBM_E_HIP, std::string("capturing the step graph failed: ") + hipGetErrorString(e));
+    }
+    c->gA = c->A;
+    return LBM_OK;
+}
+
+// n steps with no check among them. The two-pass path replays the captured block while at
+// least kGraphSteps steps remain (after one plain step when the lattices are in the other
+// roles), unless the context's stream is being captured by the caller; the rest go one by one.
+int run_steps(lbm_ctx *c, int64_t n) {
+    if (c->use_graph && n >= kGraphSteps) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        HIP_OR_FAIL(c, hipStreamIsCapturing(c->stream, &st));
+        if (st == hipStreamCaptureStatusNone) {
+            if (!c->gexec) {
+                const int rc = capture_steps(c);
+                if (rc) return rc;
+            }
+            if (c->A != c->gA) {
+                one_step(c);
+                --n;
+            }
+            for (; n >= kGraphSteps; n -= kGraphSteps) {
+                HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, c->stream));
+                c->steps += kGraphSteps;
+            }
+        }
+    }
+    for (; n > 0; --n) one_step(c);
     return LBM_OK;
 }
 
@@ -340,6 +400,8 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
             if (!c->segs.empty()) c->fused = c->segs[0].fn;
         }
     }
+    // the two-pass step replays captured blocks of steps (LBM2P_GRAPH=0: every step launched)
+    c->use_graph = !c->fused && env_int("LBM2P_GRAPH", 1) != 0;
     const size_t N = (size_t)c->g.N;
     const size_t cbytes = c->fp64 ? 8 : 4;
     hipError_t e;
@@ -472,12 +534,13 @@ int lbm_step(lbm_ctx *c, int64_t n) {
     if (!c->initialized) return fail(c, LBM_E_STATE, "lbm_step before lbm_init_fields");
     if (c->sticky) return c->sticky;
     const int ce = c->p.check_every;
-    for (int64_t t = 0; t < n; ++t) {
-        one_step(c);
-        if (ce > 0 && (t + 1) % ce == 0 && t + 1 < n) {
-            int rc = watchdog(c);
-            if (rc) return rc;
-        }
+    // runs between watchdog checks: after every ce steps of this call, and at its end
+    for (int64_t done = 0; done < n;) {
+        const int64_t run = ce > 0 ? std::min<int64_t>(n - done, ce - done % ce) : n - done;
+        int rc = run_steps(c, run);
+        if (rc) return rc;
+        done += run;
+        if (ce > 0 && done % ce == 0 && done < n && (rc = watchdog(c))) return rc;
     }
     HIP_OR_FAIL(c, hipGetLastError());
     if (ce >= 0) return watchdog(c);

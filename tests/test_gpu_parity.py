@@ -242,6 +242,90 @@ def test_repeat_run_is_bitwise_deterministic():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
+_GRAPH_CASES = {
+    2: dict(args=(2, 70, 33), kw=dict(a=0.02, T_reduced=0.8, rho_wall=0.9, mask=L.random_mask(70, 33, 1, 0.04, 11))),
+    3: dict(args=(3, 24, 20, 16), kw=dict(eos=T.PR, a=0.005046, acentric=0.344, T_reduced=0.6)),
+}
+
+
+@pytest.mark.parametrize("lattice", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_captured_step_blocks_match_launched_steps_bitwise(lattice, prec, monkeypatch):
+    # The two-pass step replays a captured block of 32 steps. Against the same steps launched
+    # one by one (LBM2P_GRAPH=0) the populations agree bit for bit after every call. The calls
+    # mix replays from either lattice, plain steps, watchdog checks inside a call
+    # (check_every 50), state reads, and a caller stream.
+    import torch
+
+    import paper_2112_01975_amd as P
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    gc = _GRAPH_CASES[lattice]
+    case = Case(*gc["args"], **gc["kw"])
+    rv, _ = case.coexistence()
+    rho_ref = rv if prec else 0.0
+    rho0, u0 = drop_case_inputs(case, min(case.nx, case.ny) / 4)
+    sims = {}
+    try:
+        for g in ("1", "0"):
+            monkeypatch.setenv("LBM2P_GRAPH", g)
+            sims[g] = P.Simulation(case.params(prec, rho_ref, check_every=50)).init(rho0, u0)
+        calls = (70, 5, 64, 33, 200, 1, 96)
+        for n in calls:
+            for g in sims:
+                sims[g].step(n)
+            pa, pb = (P.lbm_get_populations(sims[g].ctx) for g in ("1", "0"))
+            print(f"{lattice}D prec {prec}: {n} steps, equal {np.array_equal(pa, pb)}", flush=True)
+            assert np.array_equal(pa, pb), n
+        stream = torch.cuda.Stream()
+        for g in sims:
+            P.lbm_set_stream(sims[g].ctx, stream.cuda_stream)
+            sims[g].step(64)
+            P.lbm_set_stream(sims[g].ctx, None)
+        ra, Ua, ta = sims["1"].moments()
+        rb, Ub, tb = sims["0"].moments()
+        assert np.array_equal(ra, rb) and np.array_equal(Ua, Ub) and np.array_equal(ta, tb)
+        assert np.all(np.isfinite(ra))
+    finally:
+        for sim in sims.values():
+            sim.close()
+
+
+def test_steps_captured_by_the_caller_are_launched_one_by_one(monkeypatch):
+    # On a stream the caller is capturing, lbm_step launches its steps into the caller's graph
+    # instead of capturing a graph of its own. The caller's graph of 32 steps, replayed twice
+    # with eager steps between (an even number: the graph holds the lattice current at capture),
+    # matches a context that stepped eagerly, bit for bit.
+    import torch
+
+    import paper_2112_01975_amd as P
+    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    case = Case(2, 64, 40, a=0.02, T_reduced=0.8)
+    rho0, u0 = drop_case_inputs(case, 10.0)
+    cap = P.Simulation(case.params(0, 0.0, check_every=-1)).init(rho0, u0)
+    ref = P.Simulation(case.params(0, 0.0, check_every=-1)).init(rho0, u0)
+    stream = torch.cuda.Stream()
+    try:
+        P.lbm_set_stream(cap.ctx, stream.cuda_stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            P.lbm_step(cap.ctx, 32)
+        for rep in range(2):
+            with torch.cuda.stream(stream):
+                graph.replay()
+            stream.synchronize()
+            ref.step(32)
+            pa, pb = P.lbm_get_populations(cap.ctx), P.lbm_get_populations(ref.ctx)
+            print(f"caller graph replay {rep}: equal {np.array_equal(pa, pb)}", flush=True)
+            assert np.array_equal(pa, pb), rep
+            cap.step(6)
+            ref.step(6)
+        P.lbm_set_stream(cap.ctx, None)
+    finally:
+        cap.close()
+        ref.close()
+
+
 def test_watchdog_reports_divergence_and_domain():
     import paper_2112_01975_amd as P
     case = Case(2, 16, 8, a=0.02, T_reduced=0.8)
