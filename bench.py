@@ -210,17 +210,11 @@ def timed_mlups(P, torch, p, rho0, U0, steps, warmup):
     return p.N * steps / dt / 1e6, bool(np.isfinite(tot).all())
 
 
-def other_workloads(P, torch):
-    """The other full-size workloads of the path, MLUPS in both storage precisions:
-    - D2Q9 512^2 static drop R = 60 (van der Waals T/Tc = 0.8, kappa 0.02, a for W = 4,
-      tau 0.8): the whole lattice fits in the MALL, so only MLUPS are meaningful;
-    - D3Q27 512 x 256 x 256 drop impact on a textured wall (floor plus 8 x 8 pillars of
-      height 16 every 16 nodes; Peng-Robinson T/Tc = 0.6, a for W = 5, kappa 0.02;
-      nu_vapour = 15 nu_liquid with tau_liquid = 0.55 (and 0.51, FP32); wall density = vapour density;
-      drop R = 40 at (256, 128, 77) moving at -0.05 along z): MLUPS over all nodes and
-      MFLUPS over fluid nodes."""
+def d2q9_drop_leg(P, torch, steps=1000):
+    """D2Q9 512^2 static drop R = 60 (van der Waals T/Tc = 0.8, kappa 0.02, a for W = 4, tau 0.8),
+    MLUPS in both storage precisions: the whole lattice fits in the MALL, so only MLUPS are
+    meaningful."""
     import lbm_inputs as L
-    out = {}
     base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.8, 0.02, 0.8)
     a2 = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
     d2 = {}
@@ -230,9 +224,21 @@ def other_workloads(P, torch):
         rv, rl, _, _ = P.lbm_coexistence(p)
         p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
         rho0 = L.drop(512, 512, 1, 60.0, rl, rv, 4.0, noise=1e-4, seed=1003)
-        d2[name], ok = timed_mlups(P, torch, p, rho0, None, 1000, 50)
+        d2[name], ok = timed_mlups(P, torch, p, rho0, None, steps, 50)
         d2[name + "_finite"] = ok
-    out["d2q9_512x512_drop"] = {"unit": "MLUPS", "steps": 1000, **d2}
+    return {"unit": "MLUPS", "steps": steps, **d2}
+
+
+def other_workloads(P, torch):
+    """The other full-size workloads of the path, MLUPS in both storage precisions:
+    - the D2Q9 512^2 static drop (d2q9_drop_leg);
+    - D3Q27 512 x 256 x 256 drop impact on a textured wall (floor plus 8 x 8 pillars of
+      height 16 every 16 nodes; Peng-Robinson T/Tc = 0.6, a for W = 5, kappa 0.02;
+      nu_vapour = 15 nu_liquid with tau_liquid = 0.55 (and 0.51, FP32); wall density = vapour density;
+      drop R = 40 at (256, 128, 77) moving at -0.05 along z): MLUPS over all nodes and
+      MFLUPS over fluid nodes."""
+    import lbm_inputs as L
+    out = {"d2q9_512x512_drop": d2q9_drop_leg(P, torch)}
     nx, ny, nz = 512, 256, 256
     base = P.Params(P.LBM_D3Q27, 8, 8, 8, P.LBM_EOS_PR, 2.0 / 49.0, B21, 1.0, 0.344, 0.6, 0.02, 0.8)
     a3 = base.a * 0.02 / P.lbm_kappa_for_width(base, 5.0)
@@ -381,6 +387,8 @@ def main():
                     help="run only the tapered-posts leg (curved walls) and print its JSON line")
     ap.add_argument("--posts-d0", type=int, default=64,
                     help="post spacing scale D0 of the posts leg; the box is 4 D0 (150: the paper's 600^3)")
+    ap.add_argument("--d2q9-only", action="store_true",
+                    help="time only the D2Q9 512^2 drop in both precisions and print its JSON line")
     ap.add_argument("--pressure-only", action="store_true",
                     help="time only the discrete pressure tensor of the 256^3 drop and print its JSON line")
     ap.add_argument("--sizes-only", default=None, metavar="NXxNYxNZ,...",
@@ -402,6 +410,9 @@ def main():
         return
     if args.pressure_only:
         print(json.dumps({"pressure_tensor_256": pressure_tensor_leg(P, torch, args.size)}), flush=True)
+        return
+    if args.d2q9_only:
+        print(json.dumps({"d2q9_512x512_drop": d2q9_drop_leg(P, torch)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch_sweep": batch_sweep(P, torch, args.batch_steps)}), flush=True)

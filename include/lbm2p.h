@@ -142,13 +142,15 @@ int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u);
 /* Advances n time steps of eq LBGK (stream-collide with the Korteweg force and
  * halfway, or with link_q interpolated, bounce-back at solid nodes). Runs the FP64 watchdog as selected by
  * check_every; returns LBM_E_DIVERGED / LBM_E_DOMAIN when it trips. When no
- * check runs, the call only enqueues work on the context stream. Contexts on the
- * two-pass step (D2Q9, and D3Q27 grids too small for the single-pass step) capture
- * 32 steps into a HIP graph on the first call with at least 32 steps between two
- * checks. Such runs then replay that graph on the context stream, with results
+ * check runs, the call only enqueues work on the context stream. A D2Q9 step is one
+ * kernel; a D3Q27 step is the fused z-march, or on grids too small for it the moment
+ * pass and then the collide (LBM2P_TWO_PASS=1 takes the latter for both lattices;
+ * the results are the same bit for bit in D2Q9). Contexts off the fused D3Q27 step
+ * capture 32 steps into a HIP graph on the first call with at least 32 steps between
+ * two checks. Such runs then replay that graph on the context stream, with results
  * identical bit for bit; the capture uses the context's own stream. Steps are
- * launched one by one when the context stream is itself being captured, or when
- * the environment sets LBM2P_GRAPH=0. */
+ * launched one by one when the context stream is itself being captured, or when the
+ * environment sets LBM2P_GRAPH=0. */
 int lbm_step(lbm_ctx *c, int64_t n);
 
 /* Density and velocity of the current state. rho: host [N] (nullable); U: host

@@ -55,6 +55,9 @@ struct KernelSet {
     // one collide-stream step A -> B (reads rho, g written by moments)
     void (*collide)(hipStream_t, const void *A, void *B, const Geom &, const uint8_t *mask, const void *params,
                     const void *rho, const void *g);
+    // one collide-stream step A -> B in a single pass, rho and g from the tile's own pulls
+    // (D2Q9; nullptr for D3Q27)
+    void (*single)(hipStream_t, const void *A, void *B, const Geom &, const uint8_t *mask, const void *params);
     // rho and U = u + S/(2 rho) of the current state in FP64 (reads rho, g)
     void (*output)(hipStream_t, const void *A, const Geom &, const uint8_t *mask, const void *params,
                    const void *rho, const void *g, double *out_rho, double *out_U);

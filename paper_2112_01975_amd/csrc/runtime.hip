@@ -64,6 +64,7 @@ struct lbm_ctx {
     hipGraphExec_t gexec = nullptr;  // two-pass path: kGraphSteps steps captured once, replayed
     void *gA = nullptr;              // the lattice those captured steps start from
     bool use_graph = false;
+    bool single = false;             // D2Q9: single-pass step (ks.single) instead of moments + collide
     FusedLaunch fused = nullptr;     // single-pass step when available (D3Q27): the first segment's kernel
     std::vector<FusedSeg> segs;      // the launches of one fused step, over disjoint plane ranges
     bool initialized = false;
@@ -163,14 +164,23 @@ void fused_step(lbm_ctx *c) {
         sg.fn(c->stream, c->A, c->B, c->g, FusedMask{c->links, c->pflags, c->qlo}, params_ptr(c), sg.fg);
 }
 
+// the two-pass step, or the D2Q9 single pass, from lattice a into b on stream s
+void unfused_step(lbm_ctx *c, hipStream_t s, const void *a, void *b) {
+    if (c->single) {
+        c->ks.single(s, a, b, c->g, c->mask, params_ptr(c));
+    } else {
+        c->ks.moments(s, a, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
+        c->ks.collide(s, a, b, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+    }
+}
+
 int one_step(lbm_ctx *c) {
     ++c->steps;
     if (c->fused) {
         fused_step(c);
         c->folded = c->fold;
     } else {
-        c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
-        c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        unfused_step(c, c->stream, c->A, c->B);
     }
     void *t = c->A; c->A = c->B; c->B = t;
     return LBM_OK;
@@ -187,8 +197,7 @@ int capture_steps(lbm_ctx *c) {
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
     void *a = c->A, *b = c->B;
     for (int s = 0; s < kGraphSteps; ++s) {
-        c->ks.moments(c->own, a, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
-        c->ks.collide(c->own, a, b, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
+        unfused_step(c, c->own, a, b);
         std::swap(a, b);
     }
     const hipError_t le = hipGetLastError();
@@ -400,7 +409,9 @@ int lbm_create(const lbm_params *p, lbm_ctx **out) {
             if (!c->segs.empty()) c->fused = c->segs[0].fn;
         }
     }
-    // the two-pass step replays captured blocks of steps (LBM2P_GRAPH=0: every step launched)
+    // D2Q9 steps in one pass (LBM2P_TWO_PASS=1: the moment pass, then the collide)
+    c->single = c->D == 2 && !env_int("LBM2P_TWO_PASS", 0) && c->ks.single;
+    // unfused steps replay captured blocks of steps (LBM2P_GRAPH=0: every step launched)
     c->use_graph = !c->fused && env_int("LBM2P_GRAPH", 1) != 0;
     const size_t N = (size_t)c->g.N;
     const size_t cbytes = c->fp64 ? 8 : 4;
@@ -560,12 +571,14 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
     HIP_OR_FAIL(c, hipEventRecord(tot0, c->stream));
     for (int64_t t = 0; t < n; ++t) {
         HIP_OR_FAIL(c, hipEventRecord(ev[0], c->stream));
-        if (!c->fused)
+        if (!c->fused && !c->single)
             c->ks.moments(c->stream, c->A, c->g, c->mask, params_ptr(c), c->rho, c->gfl, c->partials);
         HIP_OR_FAIL(c, hipEventRecord(ev[1], c->stream));
         if (c->fused) {
             fused_step(c);
             c->folded = c->fold;
+        } else if (c->single) {
+            c->ks.single(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c));
         } else {
             c->ks.collide(c->stream, c->A, c->B, c->g, c->mask, params_ptr(c), c->rho, c->gfl);
         }
@@ -589,7 +602,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, double ms[3], int64_t launches[2]) {
     ms[0] = acc[0];
     ms[1] = acc[1];
     ms[2] = tt;
-    launches[0] = c->fused ? 0 : n;
+    launches[0] = c->fused || c->single ? 0 : n;
     launches[1] = n;
     return LBM_OK;
 }

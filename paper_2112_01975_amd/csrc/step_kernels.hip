@@ -100,7 +100,7 @@ template <int D> struct Tile {
     static constexpr int LS = LX * LY * LZ;
 };
 
-enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2, MODE_PT = 3 };
+enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2, MODE_PT = 3, MODE_SINGLE = 4 };
 
 // MODE_STEP: one collide-stream step A -> B.
 // MODE_OUT:  rho and U = u + S/(2 rho) of the state in A, FP64, into out_rho / out_U.
@@ -111,21 +111,52 @@ enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2, MODE_PT = 3 };
 //            momentum flux of the pulled (pre-collision) populations minus the one- and
 //            two-ring pseudo-potential and capillary tensors, which enter with the sign of
 //            the momentum source S = -F.
+// MODE_SINGLE: one collide-stream step A -> B in a single pass (D2Q9): the staged tile and
+//            halo nodes pull their own populations and take rho and g = rho u^3 from them, as
+//            the moment pass computes them, instead of reading the moment pass's fields.
 template <int D, class S, class C, bool MASK, int MODE>
 __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__restrict__ B, Geom g,
                                                  const uint8_t *__restrict__ mask, Params<C> p,
                                                  const C *__restrict__ rho_f, const C *__restrict__ gf,
                                                  double *__restrict__ out_rho, double *__restrict__ out_U) {
     constexpr bool OUT = MODE == MODE_OUT;
+    constexpr bool SINGLE = MODE == MODE_SINGLE;
+    static_assert(!SINGLE || D == 2, "single-pass mode: D2Q9");
     using T = Tile<D>;
     __shared__ C s_rho[T::LS];
     __shared__ C s_psi[T::LS];
+    __shared__ C s_g[SINGLE ? 2 : 1][SINGLE ? T::LS : 1];   // single pass: g_x, g_y of the staged nodes
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
     for (int e = threadIdx.x; e < T::LS; e += 256) {
         const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
         const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
         const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
-        const C r = rho_f[gx + g.px * (gy + g.ny * gz)];
+        const int gn = gx + g.px * (gy + g.ny * gz);
+        C r;
+        if constexpr (SINGLE) {
+            // the moment pass's arithmetic on this node's own pulls
+            C ga[2] = {C(0), C(0)};
+            if (MASK && mask[gn]) {
+                r = wall_density(p, gn);
+            } else {
+                Nbr<D> nb(g, gx, gy, gz);
+                C h[Lat<D>::Q];
+                gather<D, S, C, MASK>(A, g.qs, mask, nb, gn, h, p.link_q);
+                C sum, j[3];
+                moments_of<D, C>(h, sum, j);
+                r = p.rho_ref + sum;
+                const C rinv = rcp(r);
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const C ua = j[a] * rinv;
+                    ga[a] = r * ua * ua * ua;
+                }
+            }
+            s_g[0][e] = ga[0];
+            s_g[1][e] = ga[1];
+        } else {
+            r = rho_f[gn];
+        }
         s_rho[e] = r;
         s_psi[e] = signed_psi(p.eos, r);
     }
@@ -253,7 +284,11 @@ __global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__r
         for (int a = 0; a < D; ++a) u[a] = j[a] * rinv;
         const C omega = omega_of(p, rho);
         C Phi[3] = {C(0), C(0), C(0)};
-        {
+        if constexpr (SINGLE) {
+            const C cf = (C(1) - C(0.5) * omega) * C(0.5);
+            Phi[0] = cf * (s_g[0][lc + 1] - s_g[0][lc - 1]);
+            Phi[1] = cf * (s_g[1][lc + T::LX] - s_g[1][lc - T::LX]);
+        } else {
             const C cf = (C(1) - C(0.5) * omega) * C(0.5);
             Phi[0] = cf * (gf[nb.at(1, 0, 0)] - gf[nb.at(-1, 0, 0)]);
             Phi[1] = cf * (gf[(long long)g.N + nb.at(0, 1, 0)] - gf[(long long)g.N + nb.at(0, -1, 0)]);
@@ -412,6 +447,12 @@ template <int D, class S, class C, bool MASK> struct Launch {
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_STEP>), collide_grid(g), dim3(256), 0, s, (const S *)A, (S *)B, g,
                            mask, *(const Params<C> *)prm, (const C *)rho, (const C *)gfl, nullptr, nullptr);
     }
+    static void single(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm) {
+        if constexpr (D == 2)
+            hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_SINGLE>), collide_grid(g), dim3(256), 0, s,
+                               (const S *)A, (S *)B, g, mask, *(const Params<C> *)prm, (const C *)nullptr,
+                               (const C *)nullptr, nullptr, nullptr);
+    }
     static void pressure(hipStream_t s, const void *A, const Geom &g, const uint8_t *mask, const void *prm,
                          const void *rho, double *out) {
         hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_PT>), collide_grid(g), dim3(256), 0, s, (const S *)A,
@@ -429,6 +470,7 @@ template <int D, class S, class C, bool MASK> struct Launch {
         k.init = init;
         k.moments = moments;
         k.collide = collide;
+        k.single = D == 2 ? single : nullptr;
         k.output = output;
         k.pressure = pressure;
         k.moment_blocks = 0;

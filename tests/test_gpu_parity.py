@@ -248,17 +248,18 @@ _GRAPH_CASES = {
 }
 
 
-@pytest.mark.parametrize("lattice", [2, 3])
+@pytest.mark.parametrize("lattice,two_pass", [(2, "0"), (2, "1"), (3, "1")])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_captured_step_blocks_match_launched_steps_bitwise(lattice, prec, monkeypatch):
-    # The two-pass step replays a captured block of 32 steps. Against the same steps launched
-    # one by one (LBM2P_GRAPH=0) the populations agree bit for bit after every call. The calls
-    # mix replays from either lattice, plain steps, watchdog checks inside a call
-    # (check_every 50), state reads, and a caller stream.
+def test_captured_step_blocks_match_launched_steps_bitwise(lattice, two_pass, prec, monkeypatch):
+    # Steps off the fused D3Q27 kernel (the D2Q9 single pass, the two-pass step of either
+    # lattice) replay a captured block of 32 steps. Against the same steps launched one by one
+    # (LBM2P_GRAPH=0) the populations agree bit for bit after every call. The calls mix replays
+    # from either lattice, plain steps, watchdog checks inside a call (check_every 50), state
+    # reads, and a caller stream.
     import torch
 
     import paper_2112_01975_amd as P
-    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    monkeypatch.setenv("LBM2P_TWO_PASS", two_pass)
     gc = _GRAPH_CASES[lattice]
     case = Case(*gc["args"], **gc["kw"])
     rv, _ = case.coexistence()
@@ -290,7 +291,8 @@ def test_captured_step_blocks_match_launched_steps_bitwise(lattice, prec, monkey
             sim.close()
 
 
-def test_steps_captured_by_the_caller_are_launched_one_by_one(monkeypatch):
+@pytest.mark.parametrize("two_pass", ["0", "1"])
+def test_steps_captured_by_the_caller_are_launched_one_by_one(two_pass, monkeypatch):
     # On a stream the caller is capturing, lbm_step launches its steps into the caller's graph
     # instead of capturing a graph of its own. The caller's graph of 32 steps, replayed twice
     # with eager steps between (an even number: the graph holds the lattice current at capture),
@@ -298,7 +300,7 @@ def test_steps_captured_by_the_caller_are_launched_one_by_one(monkeypatch):
     import torch
 
     import paper_2112_01975_amd as P
-    monkeypatch.setenv("LBM2P_TWO_PASS", "1")
+    monkeypatch.setenv("LBM2P_TWO_PASS", two_pass)
     case = Case(2, 64, 40, a=0.02, T_reduced=0.8)
     rho0, u0 = drop_case_inputs(case, 10.0)
     cap = P.Simulation(case.params(0, 0.0, check_every=-1)).init(rho0, u0)
