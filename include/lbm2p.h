@@ -115,7 +115,8 @@ typedef struct {
                                contexts take the single-pass interpolating kernel on
                                planes within three planes of a solid node (the two-pass
                                step when the single-pass step is not available for the
-                               grid); D2Q9 takes the two-pass step; lbm_batch_create
+                               grid); D2Q9 takes it in its single-pass step (and in the
+                               two-pass step under LBM2P_TWO_PASS=1); lbm_batch_create
                                rejects it. Copied at create */
     int force_model;        /* LBM_FORCE_* (0: eq Kforce_final) */
     double force_g[4];      /* coefficients for LBM_FORCE_DUAL_RANGE ([0] = G1) and
