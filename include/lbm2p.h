@@ -146,7 +146,7 @@ int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u);
  * check runs, the call only enqueues work on the context stream. A D2Q9 step is one
  * kernel; a D3Q27 step is the fused z-march, or on grids too small for it the moment
  * pass and then the collide (LBM2P_TWO_PASS=1 takes the latter for both lattices;
- * the results are the same bit for bit in D2Q9). Contexts off the fused D3Q27 step
+ * in D2Q9 the two agree to rounding). Contexts off the fused D3Q27 step
  * capture 32 steps into a HIP graph on the first call with at least 32 steps between
  * two checks. Such runs then replay that graph on the context stream, with results
  * identical bit for bit; the capture uses the context's own stream. Steps are

