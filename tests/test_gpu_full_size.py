@@ -165,6 +165,27 @@ def test_drop_impact_512x256x256_sampled_nodes_and_precision():
 
 
 # ------------------------------------------------------------------ static-drop Laplace sweep (D2Q9 512^2)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_d2q9_512_drop_every_node_against_the_oracle(precision):
+    # The bench's D2Q9 leg at its full size (512^2 van der Waals drop, T/Tc = 0.8, kappa 0.02,
+    # W = 4, tau 0.8, R = 60, noise 1e-4), through the same path: the single-pass kernel,
+    # replayed from its captured 32-step graph (100 steps: three replays and four plain steps).
+    # Every node is compared with the oracle: FP64 within 1e-10 in density and velocity; FP32
+    # deviation storage within the bounds the batched sweep states, 1e-4 in density and 1e-5 in U.
+    import paper_2112_01975_amd as P
+    from tests.gpu_cases import max_rel, run_oracle
+    case = Case(2, 512, 512, a=0.0225, T_reduced=0.8, kappa=0.02, tau=0.8)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(512, 512, 1, 60.0, rl, rv, 4.0, noise=1e-4, seed=1003)
+    with P.Simulation(case.params(precision, rv if precision else 0.0, check_every=-1)) as s:
+        r, U, _ = s.init(rho0).step(100).moments()
+    ro, Uo, _ = run_oracle(case, rho0, None, 100)
+    er, eu = max_rel(r, ro), float(np.abs(U - Uo).max())
+    print(f"D2Q9 512^2 drop, 100 steps, precision {precision}: density {er:.2e}, U {eu:.2e}", flush=True)
+    tr, tu = (1e-10, 1e-10) if precision == 0 else (1e-4, 1e-5)
+    assert er < tr and eu < tu, (er, eu)
+
+
 def test_laplace_sweep_512_fp64_and_fp32():
     # vdW at T/Tc in {0.8, 0.9}, radii 20..100, kappa 0.02 with a = 0.0225 (W = 4 at T/Tc = 0.8),
     # tanh width 4, noise 1e-4, 20000 steps. The R = 20 drop evaporates into the 512^2 vapour
