@@ -194,6 +194,7 @@ constexpr int kGraphSteps = 32;
 // Captures kGraphSteps two-pass steps from the current lattice on the context's own stream
 // (never the caller's, which may itself be capturing). The graph holds kernels only.
 int capture_steps(lbm_ctx *c) {
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->own));   // once per context: nothing queued under the capture
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
     void *a = c->A, *b = c->B;
     for (int s = 0; s < kGraphSteps; ++s) {

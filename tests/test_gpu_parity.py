@@ -248,14 +248,15 @@ _GRAPH_CASES = {
 }
 
 
-@pytest.mark.parametrize("lattice,two_pass", [(2, "0"), (2, "1"), (3, "1")])
+@pytest.mark.parametrize("lattice,two_pass,check_every", [(2, "0", 50), (2, "1", 50), (3, "1", 50), (2, "0", -1)])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_captured_step_blocks_match_launched_steps_bitwise(lattice, two_pass, prec, monkeypatch):
+def test_captured_step_blocks_match_launched_steps_bitwise(lattice, two_pass, check_every, prec, monkeypatch):
     # Steps off the fused D3Q27 kernel (the D2Q9 single pass, the two-pass step of either
     # lattice) replay a captured block of 32 steps. Against the same steps launched one by one
     # (LBM2P_GRAPH=0) the populations agree bit for bit after every call. The calls mix replays
     # from either lattice, plain steps, watchdog checks inside a call (check_every 50), state
-    # reads, and a caller stream.
+    # reads, and a caller stream. Without checks (check_every -1) the first call leaves its
+    # plain steps queued when the next call captures its graph.
     import torch
 
     import paper_2112_01975_amd as P
@@ -269,11 +270,12 @@ def test_captured_step_blocks_match_launched_steps_bitwise(lattice, two_pass, pr
     try:
         for g in ("1", "0"):
             monkeypatch.setenv("LBM2P_GRAPH", g)
-            sims[g] = P.Simulation(case.params(prec, rho_ref, check_every=50)).init(rho0, u0)
-        calls = (70, 5, 64, 33, 200, 1, 96)
+            sims[g] = P.Simulation(case.params(prec, rho_ref, check_every=check_every)).init(rho0, u0)
+        calls = ((5, 70), 64, 33, 200, 1, 96)   # (5, 70): two calls with no read between them
         for n in calls:
             for g in sims:
-                sims[g].step(n)
+                for m in (n if isinstance(n, tuple) else (n,)):
+                    sims[g].step(m)
             pa, pb = (P.lbm_get_populations(sims[g].ctx) for g in ("1", "0"))
             print(f"{lattice}D prec {prec}: {n} steps, equal {np.array_equal(pa, pb)}", flush=True)
             assert np.array_equal(pa, pb), n
