@@ -1,5 +1,6 @@
-// step_kernels.hip -- two-pass stream-collide step of the two-phase LBGK model
-// (Sec. 2.3) for gfx950.
+// step_kernels.hip -- the D2Q9 stream-collide step in one pass, and the two-pass step
+// (D3Q27 grids the fused z-march does not take), of the two-phase LBGK model (Sec. 2.3)
+// for gfx950.
 //
 // Storage: structure of arrays A[i*qs + n], n = x + nx*(y + ny*z). The array holds
 // post-collision populations at the node that produced them; every pass pulls
@@ -10,7 +11,8 @@
 // Pass 1 (moments): rho = rho_ref + sum h_i, j = sum c_i h_i, g_a = rho u_a^3; FP64
 //   per-workgroup partial sums of mass and momentum for the watchdog.
 // Pass 2 (collide): stages rho and the signed pseudo-potential of a 64x4xZB tile
-//   plus a two-node halo in LDS, evaluates the two-ring Korteweg force
+//   plus a two-node halo in LDS (the D2Q9 single pass: a 64x8 tile whose staged nodes
+//   take rho and g from their own pulls), evaluates the two-ring Korteweg force
 //   (eq Kforce_final, or the stencil coefficients of another force model), the diagonal correction Phi (eq correction), the product-form
 //   equilibrium and extended equilibrium (eqs LBMeq, LBMstar) in cancellation-free
 //   deviation form, and the LBGK update (eq LBGK).
