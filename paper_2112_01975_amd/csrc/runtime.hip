@@ -61,7 +61,7 @@ struct lbm_ctx {
     Params<double> pd{};
     Params<float> pf{};
     KernelSet ks{};
-    hipGraphExec_t gexec = nullptr;  // two-pass path: kGraphSteps steps captured once, replayed
+    hipGraphExec_t gexec = nullptr;  // steps off the fused kernel: kGraphSteps captured once, replayed
     void *gA = nullptr;              // the lattice those captured steps start from
     bool use_graph = false;
     bool single = false;             // D2Q9: single-pass step (ks.single) instead of moments + collide
@@ -186,13 +186,14 @@ int one_step(lbm_ctx *c) {
     return LBM_OK;
 }
 
-// Two-pass steps per captured graph. Even, so that a replay leaves the two lattices in the
-// roles it found them in; 32 steps (64 kernels) make the host's launch cost per step small
-// next to a grid's own time down to a few thousand nodes.
+// Steps off the fused kernel (the D2Q9 single pass, the two-pass step) per captured graph.
+// Even, so that a replay leaves the two lattices in the roles it found them in; 32 steps
+// make the host's launch cost per step small next to a grid's own time down to a few
+// thousand nodes.
 constexpr int kGraphSteps = 32;
 
-// Captures kGraphSteps two-pass steps from the current lattice on the context's own stream
-// (never the caller's, which may itself be capturing). The graph holds kernels only.
+// Captures kGraphSteps steps from the current lattice on the context's own stream (never the
+// caller's, which may itself be capturing). The graph holds kernels only.
 int capture_steps(lbm_ctx *c) {
     HIP_OR_FAIL(c, hipStreamSynchronize(c->own));   // once per context: nothing queued under the capture
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
@@ -216,9 +217,10 @@ int capture_steps(lbm_ctx *c) {
     return LBM_OK;
 }
 
-// n steps with no check among them. The two-pass path replays the captured block while at
-// least kGraphSteps steps remain (after one plain step when the lattices are in the other
-// roles), unless the context's stream is being captured by the caller; the rest go one by one.
+// n steps with no check among them. Steps off the fused kernel replay the captured block
+// while at least kGraphSteps steps remain (after one plain step when the lattices are in the
+// other roles), unless the context's stream is being captured by the caller; the rest go one
+// by one.
 int run_steps(lbm_ctx *c, int64_t n) {
     if (c->use_graph && n >= kGraphSteps) {
         hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
