@@ -31,6 +31,8 @@ constexpr int TX = 64;   // tile width in x: one wave64 row, coalesced 256 B (FP
 constexpr int TY = 4;    // tile height in y: 4 waves per workgroup
 constexpr int HALO = 2;  // two neighbour rings
 constexpr int kSingleTY = 8;   // D2Q9 single pass: tile height (one wave per row)
+constexpr int kXcds = 8;       // MI355X: workgroups are dealt to 8 XCDs in turn
+constexpr int kXcdChunk = 128; // single pass: consecutive tiles per XCD chunk
 
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -131,22 +133,61 @@ __global__ __launch_bounds__(MODE == MODE_SINGLE ? TX * kSingleTY : TX * TY) voi
     __shared__ C s_rho[T::LS];
     __shared__ C s_psi[T::LS];
     __shared__ C s_g[SINGLE ? 2 : 1][SINGLE ? T::LS : 1];   // single pass: g_x, g_y of the staged nodes
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
-    for (int e = threadIdx.x; e < T::LS; e += NTH) {
-        const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
-        const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
-        const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
-        const int gn = gx + g.px * (gy + g.ny * gz);
-        C r;
-        if constexpr (SINGLE) {
-            // the moment pass's arithmetic on this node's own pulls
-            C ga[2] = {C(0), C(0)};
-            if (MASK && mask[gn]) {
+    // single pass: a 1-D grid. The hardware deals workgroups to the 8 XCDs in turn; the tiles,
+    // in row-major order, go to them in chunks of up to kXcdChunk consecutive tiles, so that
+    // neighbouring tiles mostly share an XCD and read each other's halo rows from its L2
+    int bx = blockIdx.x, by = blockIdx.y;
+    if constexpr (SINGLE) {
+        const int ntx = (g.nx + TX - 1) / TX, nt = ntx * ((g.ny + TYK - 1) / TYK);
+        const int per = (nt + kXcds - 1) / kXcds, ch = per < kXcdChunk ? per : kXcdChunk, b = blockIdx.x;
+        const int i = b / kXcds;
+        const int tile = ((i / ch) * kXcds + b % kXcds) * ch + i % ch;
+        if (tile >= nt) return;   // the padding of the last XCD's share (whole workgroup)
+        bx = tile % ntx;
+        by = tile / ntx;
+    }
+    const int x0 = bx * TX, y0 = by * TYK, z0 = D == 3 ? blockIdx.z * T::ZB : 0;
+    // single pass: the populations this thread pulled for its own node, kept for its update
+    C h_own[Lat<D>::Q];
+    if constexpr (SINGLE) {
+        // Staging: every thread its own tile node (wrapped past the grid's edge: those feed the
+        // stencils of the last columns and rows), and at most one of the NH halo nodes: rows 0,
+        // 1, LY-2, LY-1 of the staged tile, then columns 0, 1, LX-2, LX-1 of the rows between.
+        // Both nodes' pulls are issued before either is reduced, with the moment pass's
+        // arithmetic, to rho, s psi and g.
+        const int t = threadIdx.x, tx = t & (TX - 1), ty = t / TX;
+        constexpr int NH = T::LS - NTH;
+        static_assert(NH <= NTH, "one halo node per thread at most");
+        const bool has_halo = t < NH;
+        int lx = 0, ly = 0;
+        if (t < 4 * T::LX) {
+            const int r = t / T::LX;
+            lx = t % T::LX;
+            ly = r < 2 ? r : TYK + r;
+        } else if (has_halo) {
+            const int q = t - 4 * T::LX, c4 = q % 4;
+            ly = 2 + q / 4;
+            lx = c4 < 2 ? c4 : TX + c4;
+        }
+        const int e_own = (ty + HALO) * T::LX + tx + HALO, e_halo = ly * T::LX + lx;
+        const int ox = wrapi(x0 + tx, g.nx), oy = wrapi(y0 + ty, g.ny);
+        const int hx = wrapi(x0 - HALO + lx, g.nx), hy = wrapi(y0 - HALO + ly, g.ny);
+        const int on = ox + g.px * oy, hn = hx + g.px * hy;
+        const bool osolid = MASK && mask[on], hsolid = MASK && has_halo && mask[hn];
+        C hh[Lat<D>::Q];
+        if (!osolid) {
+            Nbr<D> nb(g, ox, oy, 0);
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, on, h_own, p.link_q);
+        }
+        if (has_halo && !hsolid) {
+            Nbr<D> nb(g, hx, hy, 0);
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, hn, hh, p.link_q);
+        }
+        auto finish = [&](int e, int gn, bool solid, const C (&h)[Lat<D>::Q]) __attribute__((always_inline)) {
+            C r, ga[2] = {C(0), C(0)};
+            if (solid) {
                 r = wall_density(p, gn);
             } else {
-                Nbr<D> nb(g, gx, gy, gz);
-                C h[Lat<D>::Q];
-                gather<D, S, C, MASK>(A, g.qs, mask, nb, gn, h, p.link_q);
                 C sum, j[3];
                 moments_of<D, C>(h, sum, j);
                 r = p.rho_ref + sum;
@@ -157,13 +198,22 @@ __global__ __launch_bounds__(MODE == MODE_SINGLE ? TX * kSingleTY : TX * TY) voi
                     ga[a] = r * ua * ua * ua;
                 }
             }
+            s_rho[e] = r;
+            s_psi[e] = signed_psi(p.eos, r);
             s_g[0][e] = ga[0];
             s_g[1][e] = ga[1];
-        } else {
-            r = rho_f[gn];
+        };
+        finish(e_own, on, osolid, h_own);
+        if (has_halo) finish(e_halo, hn, hsolid, hh);
+    } else {
+        for (int e = threadIdx.x; e < T::LS; e += NTH) {
+            const int lx = e % T::LX, t = e / T::LX, ly = t % T::LY, lz = t / T::LY;
+            const int gx = wrapi(x0 - HALO + lx, g.nx), gy = wrapi(y0 - HALO + ly, g.ny);
+            const int gz = D == 3 ? wrapi(z0 - HALO + lz, g.nz) : 0;
+            const C r = rho_f[gx + g.px * (gy + g.ny * gz)];
+            s_rho[e] = r;
+            s_psi[e] = signed_psi(p.eos, r);
         }
-        s_rho[e] = r;
-        s_psi[e] = signed_psi(p.eos, r);
     }
     __syncthreads();
     const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
@@ -280,7 +330,12 @@ __global__ __launch_bounds__(MODE == MODE_SINGLE ? TX * kSingleTY : TX * TY) voi
             });
             continue;
         } else {
-        gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h, p.link_q);
+        if constexpr (SINGLE) {
+#pragma unroll
+            for (int i = 0; i < Lat<D>::Q; ++i) h[i] = h_own[i];
+        } else {
+            gather<D, S, C, MASK>(A, g.qs, mask, nb, n, h, p.link_q);
+        }
         C drho, j[3];
         moments_of<D, C>(h, drho, j);
         C u[3] = {C(0), C(0), C(0)};
@@ -420,6 +475,13 @@ dim3 moment_grid(int D, const Geom &g) {
     return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? g.nz : 1);
 }
 
+// workgroups of the single pass: its tiles, padded to a whole number per XCD
+inline unsigned single_blocks(const Geom &g) {
+    const long long nt = (long long)((g.nx + TX - 1) / TX) * ((g.ny + kSingleTY - 1) / kSingleTY);
+    const long long per = (nt + kXcds - 1) / kXcds, ch = per < kXcdChunk ? per : kXcdChunk;
+    return (unsigned)((per + ch - 1) / ch * ch * kXcds);
+}
+
 template <int D, class S, class C, bool MASK> struct Launch {
     static dim3 collide_grid(const Geom &g) {
         return dim3((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? (g.nz + Tile<D>::ZB - 1) / Tile<D>::ZB : 1);
@@ -454,8 +516,7 @@ template <int D, class S, class C, bool MASK> struct Launch {
     }
     static void single(hipStream_t s, const void *A, void *B, const Geom &g, const uint8_t *mask, const void *prm) {
         if constexpr (D == 2)
-            hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_SINGLE>),
-                               dim3((g.nx + TX - 1) / TX, (g.ny + kSingleTY - 1) / kSingleTY, 1),
+            hipLaunchKernelGGL((k_collide<D, S, C, MASK, MODE_SINGLE>), dim3(single_blocks(g)),
                                dim3(TX * kSingleTY), 0, s,
                                (const S *)A, (S *)B, g, mask, *(const Params<C> *)prm, (const C *)nullptr,
                                (const C *)nullptr, nullptr, nullptr);
