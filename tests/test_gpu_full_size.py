@@ -186,6 +186,25 @@ def test_d2q9_512_drop_every_node_against_the_oracle(precision):
     assert er < tr and eu < tu, (er, eu)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_d2q9_ragged_grid_of_many_tiles_against_the_oracle(precision):
+    # 1100 x 1000 (ragged tiles in x and y; 2250 tiles, so the single pass deals them to the XCDs
+    # in several 128-tile chunks each and pads the last chunks with idle workgroups), a drop off
+    # the grid centre, 40 steps, every node against the oracle with the bounds above.
+    import paper_2112_01975_amd as P
+    from tests.gpu_cases import max_rel, run_oracle
+    case = Case(2, 1100, 1000, a=0.0225, T_reduced=0.8, kappa=0.02, tau=0.8)
+    rv, rl = case.coexistence()
+    rho0 = L.drop(1100, 1000, 1, 150.0, rl, rv, 4.0, centre=(700.3, 420.7, 0.0), noise=1e-4, seed=1007)
+    with P.Simulation(case.params(precision, rv if precision else 0.0, check_every=-1)) as s:
+        r, U, _ = s.init(rho0).step(40).moments()
+    ro, Uo, _ = run_oracle(case, rho0, None, 40)
+    er, eu = max_rel(r, ro), float(np.abs(U - Uo).max())
+    print(f"D2Q9 1100 x 1000 drop, 40 steps, precision {precision}: density {er:.2e}, U {eu:.2e}", flush=True)
+    tr, tu = (1e-10, 1e-10) if precision == 0 else (1e-4, 1e-5)
+    assert er < tr and eu < tu, (er, eu)
+
+
 def test_laplace_sweep_512_fp64_and_fp32():
     # vdW at T/Tc in {0.8, 0.9}, radii 20..100, kappa 0.02 with a = 0.0225 (W = 4 at T/Tc = 0.8),
     # tanh width 4, noise 1e-4, 20000 steps. The R = 20 drop evaporates into the 512^2 vapour
