@@ -210,20 +210,20 @@ def timed_mlups(P, torch, p, rho0, U0, steps, warmup):
     return p.N * steps / dt / 1e6, bool(np.isfinite(tot).all())
 
 
-def d2q9_drop_leg(P, torch, steps=1000):
-    """D2Q9 512^2 static drop R = 60 (van der Waals T/Tc = 0.8, kappa 0.02, a for W = 4, tau 0.8),
-    MLUPS in both storage precisions: the whole lattice fits in the MALL, so only MLUPS are
-    meaningful."""
+def d2q9_drop_leg(P, torch, steps=1000, n=512):
+    """D2Q9 n^2 static drop R = 60 n / 512 (van der Waals T/Tc = 0.8, kappa 0.02, a for W = 4,
+    tau 0.8), MLUPS in both storage precisions. At the workload's 512^2 the whole lattice fits
+    in the MALL, so only MLUPS are meaningful; larger n stream from HBM."""
     import lbm_inputs as L
     base = P.Params(P.LBM_D2Q9, 8, 4, 1, P.LBM_EOS_VDW, 9 / 49, B21, 1.0, 0.0, 0.8, 0.02, 0.8)
     a2 = base.a * 0.02 / P.lbm_kappa_for_width(base, 4.0)
     d2 = {}
     for prec, name in ((P.LBM_FP32_DEV, "fp32"), (P.LBM_FP64, "fp64")):
-        p = P.Params(P.LBM_D2Q9, 512, 512, 1, P.LBM_EOS_VDW, a2, B21, 1.0, 0.0, 0.8, 0.02, 0.8, precision=prec,
+        p = P.Params(P.LBM_D2Q9, n, n, 1, P.LBM_EOS_VDW, a2, B21, 1.0, 0.0, 0.8, 0.02, 0.8, precision=prec,
                      check_every=-1)
         rv, rl, _, _ = P.lbm_coexistence(p)
         p.rho_ref = rv if prec == P.LBM_FP32_DEV else 0.0
-        rho0 = L.drop(512, 512, 1, 60.0, rl, rv, 4.0, noise=1e-4, seed=1003)
+        rho0 = L.drop(n, n, 1, 60.0 * n / 512, rl, rv, 4.0, noise=1e-4, seed=1003)
         d2[name], ok = timed_mlups(P, torch, p, rho0, None, steps, 50)
         d2[name + "_finite"] = ok
     return {"unit": "MLUPS", "steps": steps, **d2}
@@ -388,7 +388,8 @@ def main():
     ap.add_argument("--posts-d0", type=int, default=64,
                     help="post spacing scale D0 of the posts leg; the box is 4 D0 (150: the paper's 600^3)")
     ap.add_argument("--d2q9-only", action="store_true",
-                    help="time only the D2Q9 512^2 drop in both precisions and print its JSON line")
+                    help="time only the D2Q9 drop (512^2, or --d2q9-size) in both precisions and print its JSON line")
+    ap.add_argument("--d2q9-size", type=int, default=512, help="grid side of the --d2q9-only leg")
     ap.add_argument("--pressure-only", action="store_true",
                     help="time only the discrete pressure tensor of the 256^3 drop and print its JSON line")
     ap.add_argument("--sizes-only", default=None, metavar="NXxNYxNZ,...",
@@ -412,7 +413,11 @@ def main():
         print(json.dumps({"pressure_tensor_256": pressure_tensor_leg(P, torch, args.size)}), flush=True)
         return
     if args.d2q9_only:
-        print(json.dumps({"d2q9_512x512_drop": d2q9_drop_leg(P, torch)}), flush=True)
+        n = args.d2q9_size
+        steps = max(20, min(1000, int(1000 * (512 / n) ** 2)))
+        # the copy probe first: its kernel is the scale of HBM counters taken on this leg
+        print(json.dumps({"attainable_copy": copy_probe(P, torch),
+                          f"d2q9_{n}x{n}_drop": d2q9_drop_leg(P, torch, steps, n)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch_sweep": batch_sweep(P, torch, args.batch_steps)}), flush=True)

@@ -88,7 +88,10 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, comman
         "# HBM traffic per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)",
         f"# command: {command}",
         f"kernel: {kernel}",
-        f"source_fingerprint: {source_fingerprint()}",
+    ]
+    if "k_fused3" in kernel:   # the fingerprint describes k_fused3's sources only
+        lines.append(f"source_fingerprint: {source_fingerprint()}")
+    lines += [
         f"dispatches_fetch: {len(kf)}",
         f"dispatches_write: {len(kw)}",
         f"copy_probe_bytes: {copy_bytes}",
